@@ -1,0 +1,236 @@
+#!/usr/bin/env python3
+"""Throughput of batched Fast Iterative Filtering on one MI355X.
+
+One step = one complete decomposition of the whole batch (every outer step:
+extrema count, mask length, Parseval scan for m, spectral apply, synthesis of
+the IMF and of the new residual), inputs resident in HBM, outputs written to
+HBM.  Prints ONE JSON line on stdout; diagnostics go to stderr.
+
+Workloads (synthetic, seeded; see siggen):
+  chirps  1024 FP32 signals, N = 65536, 2-6 AM chirps + 30 dB noise,
+          delta 1e-3, 12 IMFs (default; the headline configuration)
+  uneven  4096 FP32 signals, 7-smooth lengths log-uniform in [1024, 262144],
+          three AM tones, delta 1e-4, 12 IMFs
+  long    one FP32 signal, N = 2^24, 10 drifting tones + 20 dB pink noise,
+          delta 1e-3, 20 IMFs
+  tones3  one FP64 signal, N = 4096, three AM tones, delta 1e-3, 8 IMFs
+  plain   the chirps batch through the plain single-signal entry point
+          (one signal at a time, host loop per outer step)
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "signal samples decomposed/sec (FP32 batched FIF) vs plain, % HBM peak"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(name: str):
+    import siggen
+    if name in ("chirps", "plain"):
+        B, N = 1024, 65536
+        return dict(workload="chirps-1024x65536", lengths=[N] * B, delta=1e-3, max_imfs=12, io="f32",
+                    make=lambda: [siggen.chirps(i) for i in range(B)])
+    if name == "uneven":
+        L = siggen.uneven_lengths(4096)
+        return dict(workload="uneven-4096x[1024,262144]", lengths=list(L), delta=1e-4, max_imfs=12, io="f32",
+                    make=lambda: [siggen.uneven_signal(i, int(n)) for i, n in enumerate(L)])
+    if name == "long":
+        return dict(workload="long-1x16777216", lengths=[1 << 24], delta=1e-3, max_imfs=20, io="f32",
+                    make=lambda: [siggen.long_drift()])
+    if name == "tones3":
+        return dict(workload="tones3-1x4096", lengths=[4096], delta=1e-3, max_imfs=8, io="f64",
+                    make=lambda: [siggen.tones3()])
+    raise SystemExit("unknown workload %s" % name)
+
+
+def src_digest() -> str:
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1802_01359_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(kind: str, lengths, n_imfs, max_imfs: int, esize: int) -> float:
+    """Bytes a kernel kind must move per call of the whole decomposition, by
+    the data flow of the path (not by its implementation): half spectra are
+    (N/2+1) complex FP64 bins, signals/IMFs/remainders esize bytes/sample."""
+    L = np.asarray(lengths, dtype=np.float64)
+    n = np.asarray(n_imfs)
+    spec = (np.floor(L / 2) + 1) * 16.0
+    if kind in ("pass1_step", "single_step", "scan"):
+        act = sum(float(np.sum(spec[n > t])) for t in range(max_imfs))
+        if kind == "scan":
+            return act                                  # read the residual spectrum
+        if kind == "pass1_step":
+            return 2.0 * act                            # read + write the spectrum
+        return 2.0 * act + max_imfs * float(np.sum(L)) * esize
+    if kind == "pass2_step":
+        return max_imfs * float(np.sum(L)) * esize      # IMF rows (zeros once stopped)
+    if kind in ("pass1_fwd", "init_stats"):
+        return float(np.sum(L)) * esize
+    if kind == "pass2_fwd":
+        return float(np.sum(spec))
+    if kind == "single_fwd":
+        return float(np.sum(L)) * esize + float(np.sum(spec))
+    if kind in ("pass1_rem",):
+        return float(np.sum(spec))
+    if kind in ("pass2_rem",):
+        return float(np.sum(L)) * esize
+    if kind == "single_rem":
+        return float(np.sum(spec)) + float(np.sum(L)) * esize
+    return 0.0
+
+
+def cpu_baseline(sigs, delta, max_imfs, want: int, budget_s: float):
+    from oracle import dif
+    t0 = time.perf_counter()
+    done = 0
+    samples = 0
+    for s in sigs[:want]:
+        dif.decompose(np.asarray(s, dtype=np.float64), delta, max_imfs)
+        done += 1
+        samples += len(s)
+        if time.perf_counter() - t0 > budget_s:
+            break
+    el = time.perf_counter() - t0
+    return done, samples, el
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="chirps", choices=["chirps", "uneven", "long", "tones3", "plain"])
+    ap.add_argument("--cpu-signals", type=int, default=2, help="signals the CPU oracle decomposes")
+    ap.add_argument("--cpu-budget", type=float, default=25.0, help="seconds of CPU oracle work at most")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU; --gpus %d is not supported (signals are independent, "
+              "a multi-GPU run would shard the batch by signal)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1802_01359_amd as fif
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    W = workload(args.workload)
+    lengths = W["lengths"]
+    log("generating %s ..." % W["workload"])
+    t0 = time.perf_counter()
+    sigs = W["make"]()
+    log("  %.1f s" % (time.perf_counter() - t0))
+    dt = torch.float32 if W["io"] == "f32" else torch.float64
+    esize = 4 if W["io"] == "f32" else 8
+    packed = torch.tensor(np.concatenate(sigs), dtype=dt, device="cuda")
+    total = int(packed.numel())
+    J = W["max_imfs"]
+    delta = W["delta"]
+
+    roofline = None
+    if args.workload == "plain":
+        # plain single-signal form, one signal after another, host loop per outer step
+        N = lengths[0]
+        outs = []
+
+        def step():
+            for b in range(len(lengths)):
+                outs.append(fif.decompose(packed[b * N:(b + 1) * N], delta, J))
+                outs.clear()
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+    else:
+        plan = fif.Plan(lengths, J)
+        out = plan.alloc_outputs(dt)
+        for _ in range(args.warmup):
+            plan.run(packed, delta, out=out)
+        torch.cuda.synchronize()
+        plan.profile(True)
+        plan.profile_read()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            plan.run(packed, delta, out=out)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        prof = plan.profile_read()
+        plan.profile(False)
+        n_imfs = out.n_imfs.cpu().numpy()
+        st = out.sig_status.cpu().numpy()
+        assert np.all(st == 0), "non-finite synthetic input"
+        log("IMFs per signal: min %d mean %.2f max %d" % (n_imfs.min(), n_imfs.mean(), n_imfs.max()))
+        rows = []
+        for kind, (launches, ms) in prof.items():
+            alg = algorithmic_bytes(kind, lengths, n_imfs, J, esize) * args.steps
+            rows.append((ms, kind, launches, alg))
+        rows.sort(reverse=True)
+        tot_ms = sum(r[0] for r in rows)
+        for ms, kind, launches, alg in rows:
+            gbs = alg / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+            log("  %-12s %5d launches %9.3f ms total (%5.1f%%) %8.3f ms/launch  %7.1f GB/s algorithmic" % (
+                kind, launches, ms, 100 * ms / tot_ms, ms / launches, gbs))
+        ms, kind, launches, alg = rows[0]
+        avg_ms = ms / launches
+        alg_per_launch = alg / launches
+        achieved = alg_per_launch / (avg_ms * 1e-3) / 1e9
+        traffic = None
+        if os.path.exists(TRAFFIC_FILE):
+            try:
+                tr = json.load(open(TRAFFIC_FILE))
+                if tr.get("src_sha") == src_digest() and tr.get("kernel") == kind \
+                        and tr.get("workload") == W["workload"]:
+                    traffic = float(tr["bytes_per_launch"])
+            except (OSError, ValueError, KeyError):
+                traffic = None
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kind,
+                    "algorithmic_bytes_per_launch": alg_per_launch, "avg_launch_ms": round(avg_ms, 4),
+                    "kernel_share_of_step": round(ms / tot_ms, 3)}
+
+    value = total * args.steps / el
+    res = {
+        "metric": METRIC, "value": value, "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": W["workload"], "signals": len(lengths), "samples": total, "delta": delta,
+                   "max_imfs": J, "io_dtype": W["io"],
+                   "form": "plain single-signal" if args.workload == "plain" else "batched"},
+    }
+    if roofline is not None:
+        res["roofline"] = roofline
+    if not args.no_cpu_baseline:
+        done, samples, cel = cpu_baseline(sigs, delta, J, args.cpu_signals, args.cpu_budget)
+        res["cpu_baseline"] = {
+            "value": samples / cel, "unit": "samples/s", "cores": 1, "kind": "oracle",
+            "sample": "%d of %d signals of the same workload, full decomposition by the FP64 time-domain "
+                      "oracle (C, one thread), %.1f s" % (done, len(lengths), cel)}
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,185 @@
+/*
+ * fif.h -- C ABI of the MI355X (gfx950) Fast Iterative Filtering library.
+ *
+ * The library decomposes real signals into intrinsic mode functions (IMFs)
+ * with the direct (FFT) form of Discrete Iterative Filtering of Cicone & Zhou,
+ * "Numerical Analysis for Iterative Filtering with New Efficient
+ * Implementations Based on FFT":
+ *
+ *   - Algorithm 2 (DIF), outer loop: while the residual r has at least two
+ *     extrema, fix the filter length from the extrema count, extract one IMF,
+ *     subtract it; the last residual is returned as the remainder;
+ *   - Theorem 5 and the one-step formula of Section 4: with periodic
+ *     extension the window matrix W is circulant, so the IMF after m inner
+ *     steps is IDFT((1 - lambda)^m DFT(r)), lambda being the DFT of W's first
+ *     column (equation "Lambdas");
+ *   - Section 4, the scan over the step count: m is the smallest count whose
+ *     stop quantity SD = ||s_{m+1} - s_m|| / ||s_m|| (equation "SD") is
+ *     <= delta, here evaluated from the spectrum by Parseval's identity (the
+ *     identity used in the proof of Theorem 2).
+ *
+ * Conventions shared by every entry point:
+ *   - Readings: the window is the triangle of equation "triangular" (half
+ *     support L, sampled at integer offsets, taps summing to 1) convolved
+ *     with itself; L = ceil(2N/k) (mask_rule 0) or 2*floor(nu*N/k) (mask_rule
+ *     1, equation "Unif_Mask_length"); k counts sign changes of the nonzero
+ *     forward differences r_{i+1} - r_i (i = 0..N-2); the outer loop also
+ *     stops when max|r - mean(r)| <= floor_tau * max|s| (rounding floor) and
+ *     after max_imfs IMFs; m is capped at max_inner (flag FIF_IMF_CAP).
+ *   - Signal lengths: N >= 2 whose prime factors are all <= 7; lengths above
+ *     8192 must split as N1*N2 with N1, N2 <= 8192.  Otherwise
+ *     FIF_ERR_UNSUPPORTED_LENGTH and nothing is launched.
+ *   - Buffers: every array argument except `lengths` of fif_plan_create is a
+ *     caller-owned DEVICE pointer (HBM of the current HIP device).  The
+ *     library never frees or retains them.  Packed batches put signal b at
+ *     element offset off_b = sum_{c<b} N_c; its IMFs occupy
+ *     imfs[max_imfs*off_b .. max_imfs*off_b + max_imfs*N_b), row j = IMF j.
+ *     IMF rows at and after n_imfs[b] are zero.
+ *   - Precision: the residual spectrum, lambda, (1-lambda)^m, the stop-test
+ *     sums and the residual whose extrema are counted are FP64; the FP32
+ *     entry points read FP32 signals (widened exactly) and round IMFs and
+ *     remainders to FP32 on store.  The _f64 entry points store FP64.
+ *   - Asynchrony: fif_decompose_batched* enqueue work on `stream` and return;
+ *     outputs are valid once the caller synchronises that stream.
+ *     fif_decompose* (single signal) synchronise the stream before return.
+ *   - Errors: argument problems are detected on the host before any launch
+ *     and returned as a negative fif_status; fif_last_error() then returns a
+ *     thread-local message.  Per-signal problems (non-finite samples) are
+ *     reported in sig_status[b] and do not stop the other signals.
+ *   - Determinism: results are bitwise reproducible and do not depend on the
+ *     batch a signal is decomposed in.
+ */
+#ifndef FIF_H
+#define FIF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FIF_OK = 0,
+    FIF_ERR_INVALID_ARG = -1,
+    FIF_ERR_UNSUPPORTED_LENGTH = -2,
+    FIF_ERR_NOMEM = -3,
+    FIF_ERR_DEVICE = -4,
+    FIF_ERR_NONFINITE = -5,  /* only ever stored in sig_status[] */
+    FIF_ERR_CAPACITY = -6
+} fif_status;
+
+typedef enum {
+    /* eq. "triangular" triangle of half-support L, convolved with itself */
+    FIF_WINDOW_TRI2 = 0
+} fif_window;
+
+/* per-IMF flags */
+#define FIF_IMF_CAP 1u          /* inner count stopped at max_inner, SD > delta */
+#define FIF_IMF_REFINED 2u      /* FP64 verification moved the FP32 estimate of m */
+
+/* why a signal's outer loop ended (fif_signal_info.stop_reason) */
+#define FIF_STOP_MAX_IMFS 0
+#define FIF_STOP_FLOOR 1
+#define FIF_STOP_FEW_EXTREMA 2
+#define FIF_STOP_FAILED 3
+
+typedef struct {
+    int32_t mask_rule;   /* 0: L = ceil(2N/k)  1: L = 2*floor(nu*N/k) */
+    int32_t reserved0;
+    double nu;           /* mask_rule 1 constant, default 1.6 */
+    int64_t max_inner;   /* cap on m, default 1000000 */
+    double floor_tau;    /* rounding floor, default 1e-9 */
+} fif_options;
+
+typedef struct {
+    int64_t k;           /* extrema count of the residual the IMF came from */
+    int64_t L;           /* half-support of the triangle */
+    int64_t m;           /* inner step count */
+    double sd;           /* SD_m (FP64, Parseval) */
+    double sd_prev;      /* SD_{m-1}; +inf when m == 1 */
+    uint32_t flags;      /* FIF_IMF_* */
+    int32_t reserved;
+} fif_imf_info;
+
+typedef struct fif_plan fif_plan;
+
+/* Fill *opt with the defaults listed above. */
+void fif_options_default(fif_options* opt);
+
+/* Message of the last failing call on this host thread ("" if none). */
+const char* fif_last_error(void);
+const char* fif_status_string(fif_status s);
+
+/*
+ * Create a plan for a batch of B signals with the given lengths (HOST array
+ * of B int64) and at most max_imfs IMFs each.  The plan owns device tables
+ * (twiddles, sine tables, work lists) allocated on the current device; it
+ * does not depend on delta.  opt may be NULL (defaults).
+ */
+fif_status fif_plan_create(fif_plan** plan, const int64_t* lengths, int32_t B, int32_t max_imfs,
+                           const fif_options* opt);
+/* Bytes of device workspace fif_decompose_batched needs for this plan. */
+fif_status fif_plan_workspace_size(const fif_plan* plan, size_t* bytes);
+fif_status fif_plan_destroy(fif_plan* plan);
+
+/*
+ * Decompose the packed batch described by the plan (Algorithm 2 with the
+ * one-step formula per IMF).  signals: FP32 [sum N_b]; imfs: FP32
+ * [max_imfs * sum N_b]; remainders: FP32 [sum N_b]; n_imfs: int32 [B];
+ * info: fif_imf_info [B * max_imfs] (row-major by signal), may be NULL;
+ * sig_status: int32 [B] (FIF_OK or FIF_ERR_NONFINITE), may be NULL;
+ * workspace: >= fif_plan_workspace_size bytes, 256-byte aligned.
+ * delta > 0.  Enqueued on `stream` (a hipStream_t, NULL = null stream).
+ */
+fif_status fif_decompose_batched(fif_plan* plan, const float* signals, double delta,
+                                 float* imfs, float* remainders, int32_t* n_imfs,
+                                 fif_imf_info* info, int32_t* sig_status,
+                                 void* workspace, void* stream);
+/* Same with FP64 signals, IMFs and remainders. */
+fif_status fif_decompose_batched_f64(fif_plan* plan, const double* signals, double delta,
+                                     double* imfs, double* remainders, int32_t* n_imfs,
+                                     fif_imf_info* info, int32_t* sig_status,
+                                     void* workspace, void* stream);
+
+/*
+ * Plain single-signal form: one signal of length N, one IMF per host
+ * iteration, the host reads the signal's state after every outer step and
+ * stops launching once it has finished.  The library allocates and caches
+ * its own plan and workspace for N on the current device.  Device pointers:
+ * signal [N], imfs [max_imfs*N], remainder [N], n_imfs [1], info
+ * [max_imfs] (may be NULL).  Returns FIF_ERR_NONFINITE if the signal holds
+ * NaN or Inf (imfs zero, remainder = signal).  Synchronises `stream`.
+ */
+fif_status fif_decompose(const float* signal, int64_t N, fif_window window, double delta,
+                         int32_t max_imfs, float* imfs, float* remainder, int32_t* n_imfs,
+                         fif_imf_info* info, const fif_options* opt, void* stream);
+fif_status fif_decompose_f64(const double* signal, int64_t N, fif_window window, double delta,
+                             int32_t max_imfs, double* imfs, double* remainder, int32_t* n_imfs,
+                             fif_imf_info* info, const fif_options* opt, void* stream);
+
+/* Release the cached single-signal plans and workspaces of this process. */
+void fif_release_cache(void);
+
+/*
+ * Kernel timing.  While enabled, every later fif_decompose_batched* call on
+ * this plan brackets each kernel launch with a pair of HIP events recorded
+ * on the call's stream.  fif_plan_profile_read waits for those events,
+ * accumulates elapsed time per kernel kind since the last read into out
+ * (HOST array of cap entries, one per kind seen, in first-launch order),
+ * stores the number of kinds in *n and forgets the events.  Enabling adds
+ * two event records per launch and nothing else.
+ */
+typedef struct {
+    char name[40];       /* kernel kind, e.g. "pass1_step" */
+    int64_t launches;
+    double total_ms;
+} fif_kernel_time;
+
+fif_status fif_plan_profile(fif_plan* plan, int32_t enable);
+fif_status fif_plan_profile_read(fif_plan* plan, fif_kernel_time* out, int32_t cap, int32_t* n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FIF_H */

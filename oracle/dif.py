@@ -163,12 +163,12 @@ def decompose(s, delta: float, max_imfs: int, *, mask_rule: int = 0, nu: float =
     """Time-domain DIF decomposition of one signal (Algorithm 2), FP64.
 
     inner_form: 0 literal folded taps, 1 four periodic box sums; default picks
-    the literal form for N <= 8192 and the box form above.
+    the literal form for N <= 1024 and the box form above.
     """
     s = _f64(s)
     N = s.size
     if inner_form is None:
-        inner_form = 0 if N <= 8192 else 1
+        inner_form = 0 if N <= 1024 else 1
     opts = _Opts(mask_rule, inner_form, nu, max_inner, floor_tau)
     imfs = np.zeros((max(max_imfs, 1), N))
     rem = np.zeros(N)

@@ -1,0 +1,117 @@
+"""ctypes binding of libfif (argument marshalling only).
+
+Every step of the decomposition runs in the library's HIP kernels; torch is
+used for device memory and the current HIP stream.  Loading fails loudly
+when libfif.so has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfif.so")
+
+FIF_OK = 0
+FIF_ERR_INVALID_ARG = -1
+FIF_ERR_UNSUPPORTED_LENGTH = -2
+FIF_ERR_NOMEM = -3
+FIF_ERR_DEVICE = -4
+FIF_ERR_NONFINITE = -5
+FIF_ERR_CAPACITY = -6
+
+IMF_CAP = 1
+IMF_REFINED = 2
+
+STOP_MAX_IMFS, STOP_FLOOR, STOP_FEW_EXTREMA, STOP_FAILED = 0, 1, 2, 3
+
+# symbols declared in include/fif.h
+EXPORTED = (
+    "fif_options_default", "fif_last_error", "fif_status_string",
+    "fif_plan_create", "fif_plan_workspace_size", "fif_plan_destroy",
+    "fif_decompose_batched", "fif_decompose_batched_f64",
+    "fif_decompose", "fif_decompose_f64", "fif_release_cache",
+    "fif_plan_profile", "fif_plan_profile_read",
+)
+
+
+class FifError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("fif status %d: %s" % (status, message))
+        self.status = status
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("mask_rule", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("nu", ctypes.c_double),
+                ("max_inner", ctypes.c_int64), ("floor_tau", ctypes.c_double)]
+
+
+class KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 40), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
+
+
+IMF_INFO_DTYPE = np.dtype([("k", "<i8"), ("L", "<i8"), ("m", "<i8"), ("sd", "<f8"), ("sd_prev", "<f8"),
+                           ("flags", "<u4"), ("reserved", "<i4")])
+assert IMF_INFO_DTYPE.itemsize == 48
+
+
+@dataclass
+class Options:
+    mask_rule: int = 0
+    nu: float = 1.6
+    max_inner: int = 1_000_000
+    floor_tau: float = 1e-9
+
+    def c(self) -> _Options:
+        return _Options(self.mask_rule, 0, self.nu, self.max_inner, self.floor_tau)
+
+
+_lib = None
+
+
+def load():
+    """Load libfif.so; raises if it is missing (no fallback path exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libfif.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    lib.fif_options_default.argtypes = [ctypes.POINTER(_Options)]
+    lib.fif_options_default.restype = None
+    lib.fif_last_error.restype = ctypes.c_char_p
+    lib.fif_last_error.argtypes = []
+    lib.fif_status_string.restype = ctypes.c_char_p
+    lib.fif_status_string.argtypes = [ctypes.c_int]
+    lib.fif_plan_create.restype = ctypes.c_int
+    lib.fif_plan_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(i64), i32, i32, ctypes.POINTER(_Options)]
+    lib.fif_plan_workspace_size.restype = ctypes.c_int
+    lib.fif_plan_workspace_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    lib.fif_plan_destroy.restype = ctypes.c_int
+    lib.fif_plan_destroy.argtypes = [vp]
+    for name in ("fif_decompose_batched", "fif_decompose_batched_f64"):
+        f = getattr(lib, name)
+        f.restype = ctypes.c_int
+        f.argtypes = [vp, vp, dbl, vp, vp, vp, vp, vp, vp, vp]
+    for name in ("fif_decompose", "fif_decompose_f64"):
+        f = getattr(lib, name)
+        f.restype = ctypes.c_int
+        f.argtypes = [vp, i64, ctypes.c_int, dbl, i32, vp, vp, vp, vp, ctypes.POINTER(_Options), vp]
+    lib.fif_release_cache.restype = None
+    lib.fif_release_cache.argtypes = []
+    lib.fif_plan_profile.restype = ctypes.c_int
+    lib.fif_plan_profile.argtypes = [vp, i32]
+    lib.fif_plan_profile_read.restype = ctypes.c_int
+    lib.fif_plan_profile_read.argtypes = [vp, ctypes.POINTER(KernelTime), i32, ctypes.POINTER(i32)]
+    _lib = lib
+    return lib
+
+
+def check(status: int) -> None:
+    if status != FIF_OK:
+        msg = load().fif_last_error().decode(errors="replace")
+        raise FifError(status, msg)

@@ -1,0 +1,822 @@
+// Host runtime of libfif: plans (radix factorisation, four-step split,
+// tiles, work lists, device twiddle and sine tables), workspace layout, and
+// the launch sequence of the batched and single-signal decompositions.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/fif.h"
+#include "fif_kernels.hpp"
+
+using namespace fif;
+
+namespace {
+
+thread_local std::string g_err;
+
+fif_status fail(fif_status s, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(FIF_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));        \
+    } while (0)
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// prime factors <= 7 only
+bool smooth7(int64_t n)
+{
+    if (n < 1) return false;
+    for (int p : {2, 3, 5, 7})
+        while (n % p == 0) n /= p;
+    return n == 1;
+}
+
+bool make_subfft(int64_t n, SubFft& f)
+{
+    std::memset(&f, 0, sizeof(f));
+    f.n = (int32_t)n;
+    int64_t r = n;
+    int e2 = 0;
+    while (r % 2 == 0) { r /= 2; ++e2; }
+    std::vector<int> rad;
+    while (e2 >= 3) { rad.push_back(8); e2 -= 3; }
+    if (e2 == 2) rad.push_back(4);
+    if (e2 == 1) rad.push_back(2);
+    for (int p : {7, 5, 3})
+        while (r % p == 0) { rad.push_back(p); r /= p; }
+    if (r != 1 || (int)rad.size() > kMaxRadices) return false;
+    f.nrad = (int32_t)rad.size();
+    for (size_t i = 0; i < rad.size(); ++i) f.rad[i] = (int8_t)rad[i];
+    return true;
+}
+
+int64_t largest_divisor_at_most(int64_t n, int64_t cap)
+{
+    for (int64_t d = std::min(n, cap); d >= 1; --d)
+        if (n % d == 0) return d;
+    return 1;
+}
+
+struct DevBuf {
+    void* p = nullptr;
+    ~DevBuf() { if (p) (void)hipFree(p); }
+};
+
+}  // namespace
+
+struct fif_plan {
+    int device = 0;
+    int32_t B = 0, max_imfs = 0;
+    fif_options opt;
+    std::vector<int64_t> lengths;
+    std::vector<SigDesc> sigs;
+    std::vector<LenPlan> lens;
+    std::vector<Work> w_init, w_single, w_p1, w_p2;
+    std::vector<int32_t> scan_small, scan_big;
+    std::vector<int64_t> gscr_off;
+    size_t lds_single = 0, lds_p1 = 0, lds_p2 = 0;
+    // device copies (one allocation)
+    DevBuf dmeta, dtabs;
+    SigDesc* d_sigs = nullptr;
+    LenPlan* d_lens = nullptr;
+    Work *d_init = nullptr, *d_single = nullptr, *d_p1 = nullptr, *d_p2 = nullptr;
+    int32_t *d_scan_small = nullptr, *d_scan_big = nullptr;
+    int64_t* d_gscr_off = nullptr;
+    double* d_dtab = nullptr;
+    double2* d_ctab = nullptr;
+    // workspace layout (byte offsets)
+    size_t ws_state = 0, ws_spec0 = 0, ws_spec1 = 0, ws_inter = 0, ws_parts = 0, ws_gscr = 0, ws_total = 0;
+    // kernel timing (fif_plan_profile)
+    struct Rec {
+        int kind;
+        hipEvent_t a, b;
+    };
+    bool prof = false;
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    std::vector<std::string> kinds;
+    ~fif_plan()
+    {
+        for (auto& r : recs) {
+            pool.push_back(r.a);
+            pool.push_back(r.b);
+        }
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+namespace {
+
+fif_status set_lds_limits()
+{
+    static std::once_flag once;
+    static hipError_t err = hipSuccess;
+    std::call_once(once, [] {
+        const int lim = kFftCap * (int)sizeof(double2);
+        auto set = [&](const void* f) {
+            hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+            if (e != hipSuccess && err == hipSuccess) err = e;
+        };
+        set((const void*)k_single<MODE_FORWARD, float, float>);
+        set((const void*)k_single<MODE_STEP, float, float>);
+        set((const void*)k_single<MODE_REMAINDER, float, float>);
+        set((const void*)k_single<MODE_FORWARD, double, double>);
+        set((const void*)k_single<MODE_STEP, double, double>);
+        set((const void*)k_single<MODE_REMAINDER, double, double>);
+        set((const void*)k_pass1<MODE_FORWARD, float>);
+        set((const void*)k_pass1<MODE_STEP, float>);
+        set((const void*)k_pass1<MODE_REMAINDER, float>);
+        set((const void*)k_pass1<MODE_FORWARD, double>);
+        set((const void*)k_pass1<MODE_STEP, double>);
+        set((const void*)k_pass1<MODE_REMAINDER, double>);
+        set((const void*)k_pass2<MODE_FORWARD, float, float>);
+        set((const void*)k_pass2<MODE_STEP, float, float>);
+        set((const void*)k_pass2<MODE_REMAINDER, float, float>);
+        set((const void*)k_pass2<MODE_FORWARD, double, double>);
+        set((const void*)k_pass2<MODE_STEP, double, double>);
+        set((const void*)k_pass2<MODE_REMAINDER, double, double>);
+        set((const void*)k_scan<kScanBinsPerThread>);
+    });
+    if (err != hipSuccess) return fail(FIF_ERR_DEVICE, "hipFuncSetAttribute: %s", hipGetErrorString(err));
+    return FIF_OK;
+}
+
+fif_status validate_opts(const fif_options& o)
+{
+    if (o.mask_rule != 0 && o.mask_rule != 1) return fail(FIF_ERR_INVALID_ARG, "mask_rule must be 0 or 1");
+    if (o.mask_rule == 1 && !(o.nu > 0.0 && std::isfinite(o.nu)))
+        return fail(FIF_ERR_INVALID_ARG, "nu must be positive and finite");
+    if (o.max_inner < 1 || o.max_inner > (int64_t)1 << 40)
+        return fail(FIF_ERR_INVALID_ARG, "max_inner must be in [1, 2^40]");
+    if (!(o.floor_tau >= 0.0 && std::isfinite(o.floor_tau)))
+        return fail(FIF_ERR_INVALID_ARG, "floor_tau must be finite and >= 0");
+    return FIF_OK;
+}
+
+// Radix plans, four-step split and tiles of one distinct length.
+fif_status plan_length(int64_t N, LenPlan& lp)
+{
+    std::memset(&lp, 0, sizeof(lp));
+    lp.N = N;
+    if (N <= kFftCap) {
+        lp.two_pass = 0;
+        lp.N1 = 1;
+        lp.N2 = (int32_t)N;
+        if (!make_subfft(N, lp.f1))
+            return fail(FIF_ERR_UNSUPPORTED_LENGTH, "length %lld has a prime factor > 7", (long long)N);
+        lp.TC = lp.TR = 1;
+        return FIF_OK;
+    }
+    // N = N1 * N2, both <= cap, max(N1, N2) smallest
+    int64_t best1 = -1;
+    for (int64_t n2 = 1; n2 <= kFftCap; ++n2) {
+        if (N % n2) continue;
+        const int64_t n1 = N / n2;
+        if (n1 > kFftCap) continue;
+        if (best1 < 0 || std::max(n1, n2) < std::max(best1, N / best1)) best1 = n1;
+    }
+    if (best1 < 0)
+        return fail(FIF_ERR_UNSUPPORTED_LENGTH, "length %lld does not split into two factors <= %d",
+                    (long long)N, kFftCap);
+    lp.two_pass = 1;
+    lp.N1 = (int32_t)best1;
+    lp.N2 = (int32_t)(N / best1);
+    if (!make_subfft(lp.N2, lp.f1) || !make_subfft(lp.N1, lp.f2))
+        return fail(FIF_ERR_UNSUPPORTED_LENGTH, "length %lld has a prime factor > 7", (long long)N);
+    lp.TC = (int32_t)largest_divisor_at_most(lp.N1, kFftCap / lp.N2);
+    lp.TR = (int32_t)largest_divisor_at_most(lp.N2, kFftCap / lp.N1);
+    int64_t split = 1;
+    while (split * split < N) split *= 2;
+    lp.big_split = (int32_t)split;
+    return FIF_OK;
+}
+
+template <typename T>
+T* upload(char* dbase, size_t off, const std::vector<T>& v, std::vector<char>& host)
+{
+    if (!v.empty()) std::memcpy(host.data() + off, v.data(), v.size() * sizeof(T));
+    return reinterpret_cast<T*>(dbase + off);
+}
+
+}  // namespace
+
+extern "C" {
+
+void fif_options_default(fif_options* opt)
+{
+    if (!opt) return;
+    opt->mask_rule = 0;
+    opt->reserved0 = 0;
+    opt->nu = 1.6;
+    opt->max_inner = 1000000;
+    opt->floor_tau = 1e-9;
+}
+
+const char* fif_last_error(void) { return g_err.c_str(); }
+
+const char* fif_status_string(fif_status s)
+{
+    switch (s) {
+    case FIF_OK: return "ok";
+    case FIF_ERR_INVALID_ARG: return "invalid argument";
+    case FIF_ERR_UNSUPPORTED_LENGTH: return "unsupported length";
+    case FIF_ERR_NOMEM: return "out of memory";
+    case FIF_ERR_DEVICE: return "device error";
+    case FIF_ERR_NONFINITE: return "non-finite input";
+    case FIF_ERR_CAPACITY: return "capacity exceeded";
+    }
+    return "unknown status";
+}
+
+fif_status fif_plan_create(fif_plan** out, const int64_t* lengths, int32_t B, int32_t max_imfs,
+                           const fif_options* opt_in)
+{
+    g_err.clear();
+    if (!out) return fail(FIF_ERR_INVALID_ARG, "plan pointer is null");
+    *out = nullptr;
+    if (!lengths || B < 1) return fail(FIF_ERR_INVALID_ARG, "need at least one signal length");
+    if (max_imfs < 1 || max_imfs > 4096) return fail(FIF_ERR_INVALID_ARG, "max_imfs must be in [1, 4096]");
+    fif_options opt;
+    fif_options_default(&opt);
+    if (opt_in) opt = *opt_in;
+    fif_status st = validate_opts(opt);
+    if (st) return st;
+
+    std::unique_ptr<fif_plan> p(new fif_plan());
+    p->B = B;
+    p->max_imfs = max_imfs;
+    p->opt = opt;
+    p->lengths.assign(lengths, lengths + B);
+
+    std::map<int64_t, int32_t> len_id;
+    for (int32_t b = 0; b < B; ++b) {
+        const int64_t N = lengths[b];
+        if (N < 2) return fail(FIF_ERR_INVALID_ARG, "signal %d: length %lld < 2", b, (long long)N);
+        if (N > ((int64_t)1 << 30)) return fail(FIF_ERR_UNSUPPORTED_LENGTH, "signal %d too long", b);
+        if (!smooth7(N))
+            return fail(FIF_ERR_UNSUPPORTED_LENGTH, "signal %d: length %lld has a prime factor > 7", b,
+                        (long long)N);
+        if (!len_id.count(N)) {
+            LenPlan lp;
+            st = plan_length(N, lp);
+            if (st) return st;
+            len_id[N] = (int32_t)p->lens.size();
+            p->lens.push_back(lp);
+        }
+    }
+
+    // all host-side validation is done: from here on the device is used
+    st = set_lds_limits();
+    if (st) return st;
+    HIP_TRY(hipGetDevice(&p->device));
+
+    // tables: sines (doubles) and twiddles (complex), laid out per length
+    int64_t dcount = 0, ccount = 0;
+    struct RootReq { int64_t off, den, count, stride; };
+    std::vector<RootReq> roots;
+    std::vector<std::pair<int64_t, int64_t>> sins;  // (offset, N)
+    auto add_sub = [&](SubFft& f) {
+        f.tw_off = (int32_t)ccount;
+        int64_t ns = 1;
+        for (int i = 0; i < f.nrad; ++i) {
+            roots.push_back({ccount, ns * f.rad[i], ns, 1});
+            ccount += ns;
+            ns *= f.rad[i];
+        }
+    };
+    for (auto& lp : p->lens) {
+        lp.sin_off = dcount;
+        sins.push_back({dcount, lp.N});
+        dcount += lp.N / 2 + 1;
+        add_sub(lp.f1);
+        if (lp.two_pass) {
+            add_sub(lp.f2);
+            lp.big_lo_off = ccount;
+            roots.push_back({ccount, lp.N, lp.big_split, 1});
+            ccount += lp.big_split;
+            lp.big_hi_off = ccount;
+            const int64_t nhi = (lp.N + lp.big_split - 1) / lp.big_split;
+            roots.push_back({ccount, lp.N, nhi, lp.big_split});
+            ccount += nhi;
+        }
+    }
+
+    // signals, work lists, workspace sizes
+    int64_t off = 0, spec = 0, inter = 0, gscr = 0;
+    int32_t parts = 0;
+    for (int32_t b = 0; b < B; ++b) {
+        const int64_t N = lengths[b];
+        const int32_t lid = len_id[N];
+        const LenPlan& lp = p->lens[lid];
+        SigDesc d;
+        d.N = N;
+        d.off = off;
+        d.spec_off = spec;
+        d.inter_off = lp.two_pass ? inter : 0;
+        d.len_id = lid;
+        d.part_off = parts;
+        d.n_parts = lp.two_pass ? (int32_t)(N / lp.TR) : 1;
+        d.n_init_parts = (int32_t)((N + kFftCap - 1) / kFftCap);
+        p->sigs.push_back(d);
+        off += N;
+        spec += N / 2 + 1;
+        if (lp.two_pass) inter += N;
+        parts += std::max(d.n_parts, d.n_init_parts);
+        for (int32_t t = 0; t < d.n_init_parts; ++t) p->w_init.push_back({b, t});
+        if (!lp.two_pass) {
+            p->w_single.push_back({b, 0});
+            p->lds_single = std::max(p->lds_single, (size_t)N * sizeof(double2));
+        } else {
+            for (int32_t t = 0; t < lp.N1 / lp.TC; ++t) p->w_p1.push_back({b, t});
+            for (int32_t t = 0; t < lp.N2 / lp.TR; ++t) p->w_p2.push_back({b, t});
+            p->lds_p1 = std::max(p->lds_p1, (size_t)lp.TC * lp.N2 * sizeof(double2));
+            p->lds_p2 = std::max(p->lds_p2, (size_t)lp.TR * lp.N1 * sizeof(double2));
+        }
+        if (N / 2 <= (int64_t)kScanBinsPerThread * kScanThreads) {
+            p->scan_small.push_back(b);
+            p->gscr_off.push_back(-1);
+        } else {
+            p->scan_big.push_back(b);
+            p->gscr_off.push_back(gscr);
+            gscr += 3 * (N / 2);
+        }
+    }
+
+    size_t ws = 0;
+    p->ws_state = ws = align_up(ws, 256);
+    ws += sizeof(SigState) * (size_t)B;
+    p->ws_spec0 = ws = align_up(ws, 256);
+    ws += sizeof(double2) * (size_t)spec;
+    p->ws_spec1 = ws = align_up(ws, 256);
+    ws += sizeof(double2) * (size_t)spec;
+    p->ws_inter = ws = align_up(ws, 256);
+    ws += sizeof(double2) * (size_t)inter;
+    p->ws_parts = ws = align_up(ws, 256);
+    ws += sizeof(RunState) * (size_t)parts;
+    p->ws_gscr = ws = align_up(ws, 256);
+    ws += sizeof(float) * (size_t)gscr;
+    p->ws_total = align_up(ws, 256);
+
+    // metadata upload
+    size_t mo = 0;
+    size_t o_sigs = (mo = align_up(mo, 256));
+    mo += sizeof(SigDesc) * p->sigs.size();
+    size_t o_lens = (mo = align_up(mo, 256));
+    mo += sizeof(LenPlan) * p->lens.size();
+    size_t o_init = (mo = align_up(mo, 256));
+    mo += sizeof(Work) * p->w_init.size();
+    size_t o_single = (mo = align_up(mo, 256));
+    mo += sizeof(Work) * p->w_single.size();
+    size_t o_p1 = (mo = align_up(mo, 256));
+    mo += sizeof(Work) * p->w_p1.size();
+    size_t o_p2 = (mo = align_up(mo, 256));
+    mo += sizeof(Work) * p->w_p2.size();
+    size_t o_ss = (mo = align_up(mo, 256));
+    mo += sizeof(int32_t) * p->scan_small.size();
+    size_t o_sb = (mo = align_up(mo, 256));
+    mo += sizeof(int32_t) * p->scan_big.size();
+    size_t o_go = (mo = align_up(mo, 256));
+    mo += sizeof(int64_t) * p->gscr_off.size();
+    mo = align_up(mo, 256);
+    std::vector<char> host(mo, 0);
+    if (hipMalloc(&p->dmeta.p, mo) != hipSuccess) return fail(FIF_ERR_NOMEM, "plan metadata allocation failed");
+    char* db = (char*)p->dmeta.p;
+    p->d_sigs = upload(db, o_sigs, p->sigs, host);
+    p->d_lens = upload(db, o_lens, p->lens, host);
+    p->d_init = upload(db, o_init, p->w_init, host);
+    p->d_single = upload(db, o_single, p->w_single, host);
+    p->d_p1 = upload(db, o_p1, p->w_p1, host);
+    p->d_p2 = upload(db, o_p2, p->w_p2, host);
+    p->d_scan_small = upload(db, o_ss, p->scan_small, host);
+    p->d_scan_big = upload(db, o_sb, p->scan_big, host);
+    p->d_gscr_off = upload(db, o_go, p->gscr_off, host);
+    HIP_TRY(hipMemcpy(p->dmeta.p, host.data(), mo, hipMemcpyHostToDevice));
+
+    // tables, computed on the device in FP64
+    const size_t tab_bytes = align_up(sizeof(double) * (size_t)dcount, 256) + sizeof(double2) * (size_t)ccount + 256;
+    if (hipMalloc(&p->dtabs.p, tab_bytes) != hipSuccess) return fail(FIF_ERR_NOMEM, "plan table allocation failed");
+    p->d_dtab = (double*)p->dtabs.p;
+    p->d_ctab = (double2*)((char*)p->dtabs.p + align_up(sizeof(double) * (size_t)dcount, 256));
+    for (auto& s : sins) {
+        const int64_t cnt = s.second / 2 + 1;
+        k_fill_sin<<<(unsigned)((cnt + 255) / 256), 256>>>(p->d_dtab + s.first, s.second, cnt);
+    }
+    for (auto& r : roots) {
+        if (r.count <= 0) continue;
+        k_fill_roots<<<(unsigned)((r.count + 255) / 256), 256>>>(p->d_ctab + r.off, r.den, r.count, r.stride);
+    }
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipDeviceSynchronize());
+    *out = p.release();
+    return FIF_OK;
+}
+
+fif_status fif_plan_workspace_size(const fif_plan* plan, size_t* bytes)
+{
+    if (!plan || !bytes) return fail(FIF_ERR_INVALID_ARG, "null argument");
+    *bytes = plan->ws_total;
+    return FIF_OK;
+}
+
+fif_status fif_plan_destroy(fif_plan* plan)
+{
+    delete plan;
+    return FIF_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+hipEvent_t take_event(fif_plan* p)
+{
+    if (!p->pool.empty()) {
+        hipEvent_t e = p->pool.back();
+        p->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Records events around one launch when profiling is on.
+struct Timed {
+    fif_plan* p;
+    hipStream_t s;
+    fif_plan::Rec r;
+    bool on;
+    Timed(const fif_plan* pc, const char* kind, hipStream_t st) : p(const_cast<fif_plan*>(pc)), s(st), on(pc->prof)
+    {
+        if (!on) return;
+        int id = -1;
+        for (size_t i = 0; i < p->kinds.size(); ++i)
+            if (p->kinds[i] == kind) id = (int)i;
+        if (id < 0) {
+            id = (int)p->kinds.size();
+            p->kinds.push_back(kind);
+        }
+        r.kind = id;
+        r.a = take_event(p);
+        r.b = take_event(p);
+        if (!r.a || !r.b) {
+            on = false;
+            return;
+        }
+        (void)hipEventRecord(r.a, s);
+    }
+    ~Timed()
+    {
+        if (!on) return;
+        (void)hipEventRecord(r.b, s);
+        p->recs.push_back(r);
+    }
+};
+
+struct Bound {
+    StepArgs sa;
+    ScanArgs sc;
+    SigState* state;
+};
+
+Bound bind(const fif_plan* p, void* ws, double delta, fif_imf_info* info)
+{
+    char* w = (char*)ws;
+    Bound b;
+    b.state = (SigState*)(w + p->ws_state);
+    StepArgs& A = b.sa;
+    A.sigs = p->d_sigs;
+    A.lens = p->d_lens;
+    A.work = nullptr;
+    A.st = b.state;
+    A.dtab = p->d_dtab;
+    A.ctab = p->d_ctab;
+    A.spec0 = (double2*)(w + p->ws_spec0);
+    A.spec1 = (double2*)(w + p->ws_spec1);
+    A.inter = (double2*)(w + p->ws_inter);
+    A.parts = (RunState*)(w + p->ws_parts);
+    A.t = 0;
+    A.max_imfs = p->max_imfs;
+    ScanArgs& S = b.sc;
+    S.sigs = p->d_sigs;
+    S.lens = p->d_lens;
+    S.list = nullptr;
+    S.st = b.state;
+    S.parts = A.parts;
+    S.dtab = p->d_dtab;
+    S.spec0 = A.spec0;
+    S.spec1 = A.spec1;
+    S.gscr = (float*)(w + p->ws_gscr);
+    S.gscr_off = p->d_gscr_off;
+    S.info = info;
+    S.t = 0;
+    S.max_imfs = p->max_imfs;
+    S.delta = delta;
+    S.mask_rule = p->opt.mask_rule;
+    S.nu = p->opt.nu;
+    S.max_inner = p->opt.max_inner;
+    S.floor_tau = p->opt.floor_tau;
+    return b;
+}
+
+template <typename T>
+void launch_init(const fif_plan* p, Bound& b, const T* x, hipStream_t s)
+{
+    {
+        Timed tm(p, "reset", s);
+        k_reset_state<<<(p->B + 255) / 256, 256, 0, s>>>(b.state, p->B);
+    }
+    if (!p->w_init.empty()) {
+        Timed tm(p, "init_stats", s);
+        k_init_stats<T><<<(unsigned)p->w_init.size(), kFftThreads, 0, s>>>(p->d_sigs, p->d_init, x, b.sa.parts);
+    }
+    StepArgs A = b.sa;
+    if (!p->w_single.empty()) {
+        A.work = p->d_single;
+        Timed tm(p, "single_fwd", s);
+        k_single<MODE_FORWARD, T, T><<<(unsigned)p->w_single.size(), kFftThreads, p->lds_single, s>>>(A, x, nullptr,
+                                                                                                     nullptr);
+    }
+    if (!p->w_p1.empty()) {
+        A.work = p->d_p1;
+        {
+            Timed tm(p, "pass1_fwd", s);
+            k_pass1<MODE_FORWARD, T><<<(unsigned)p->w_p1.size(), kFftThreads, p->lds_p1, s>>>(A, x);
+        }
+        A.work = p->d_p2;
+        Timed tm(p, "pass2_fwd", s);
+        k_pass2<MODE_FORWARD, T, T><<<(unsigned)p->w_p2.size(), kFftThreads, p->lds_p2, s>>>(A, x, nullptr, nullptr);
+    }
+}
+
+template <typename T>
+void launch_step(const fif_plan* p, Bound& b, int t, const T* x, T* imfs, hipStream_t s)
+{
+    ScanArgs S = b.sc;
+    S.t = t;
+    if (!p->scan_small.empty()) {
+        S.list = p->d_scan_small;
+        Timed tm(p, "scan", s);
+        k_scan<kScanBinsPerThread><<<(unsigned)p->scan_small.size(), kScanThreads,
+                                     sizeof(float) * kScanBinsPerThread * kScanThreads, s>>>(S);
+    }
+    if (!p->scan_big.empty()) {
+        S.list = p->d_scan_big;
+        Timed tm(p, "scan_big", s);
+        k_scan<0><<<(unsigned)p->scan_big.size(), kScanThreads, 0, s>>>(S);
+    }
+    StepArgs A = b.sa;
+    A.t = t;
+    if (!p->w_single.empty()) {
+        A.work = p->d_single;
+        Timed tm(p, "single_step", s);
+        k_single<MODE_STEP, T, T><<<(unsigned)p->w_single.size(), kFftThreads, p->lds_single, s>>>(A, x, imfs, nullptr);
+    }
+    if (!p->w_p1.empty()) {
+        A.work = p->d_p1;
+        {
+            Timed tm(p, "pass1_step", s);
+            k_pass1<MODE_STEP, T><<<(unsigned)p->w_p1.size(), kFftThreads, p->lds_p1, s>>>(A, x);
+        }
+        A.work = p->d_p2;
+        Timed tm(p, "pass2_step", s);
+        k_pass2<MODE_STEP, T, T><<<(unsigned)p->w_p2.size(), kFftThreads, p->lds_p2, s>>>(A, x, imfs, nullptr);
+    }
+}
+
+template <typename T>
+void launch_final(const fif_plan* p, Bound& b, const T* x, T* rem, int32_t* n_imfs, int32_t* sig_status,
+                  fif_imf_info* info, hipStream_t s)
+{
+    {
+        Timed tm(p, "finalize", s);
+        k_finalize<<<(p->B + 255) / 256, 256, 0, s>>>(b.state, p->B, p->max_imfs, n_imfs, sig_status, info);
+    }
+    StepArgs A = b.sa;
+    if (!p->w_single.empty()) {
+        A.work = p->d_single;
+        Timed tm(p, "single_rem", s);
+        k_single<MODE_REMAINDER, T, T><<<(unsigned)p->w_single.size(), kFftThreads, p->lds_single, s>>>(A, x, nullptr,
+                                                                                                       rem);
+    }
+    if (!p->w_p1.empty()) {
+        A.work = p->d_p1;
+        {
+            Timed tm(p, "pass1_rem", s);
+            k_pass1<MODE_REMAINDER, T><<<(unsigned)p->w_p1.size(), kFftThreads, p->lds_p1, s>>>(A, x);
+        }
+        A.work = p->d_p2;
+        Timed tm(p, "pass2_rem", s);
+        k_pass2<MODE_REMAINDER, T, T><<<(unsigned)p->w_p2.size(), kFftThreads, p->lds_p2, s>>>(A, x, nullptr, rem);
+    }
+}
+
+template <typename T>
+fif_status batched(fif_plan* p, const T* x, double delta, T* imfs, T* rem, int32_t* n_imfs, fif_imf_info* info,
+                   int32_t* sig_status, void* ws, void* stream)
+{
+    g_err.clear();
+    if (!p) return fail(FIF_ERR_INVALID_ARG, "plan is null");
+    if (!x || !imfs || !rem || !n_imfs || !ws) return fail(FIF_ERR_INVALID_ARG, "null buffer argument");
+    if (!(delta > 0.0) || !std::isfinite(delta)) return fail(FIF_ERR_INVALID_ARG, "delta must be > 0 and finite");
+    if (((uintptr_t)ws) % 256) return fail(FIF_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != p->device) return fail(FIF_ERR_INVALID_ARG, "plan was created on device %d, current is %d", p->device, dev);
+    hipStream_t s = (hipStream_t)stream;
+    Bound b = bind(p, ws, delta, info);
+    launch_init<T>(p, b, x, s);
+    for (int t = 0; t < p->max_imfs; ++t) launch_step<T>(p, b, t, x, imfs, s);
+    launch_final<T>(p, b, x, rem, n_imfs, sig_status, info, s);
+    HIP_TRY(hipGetLastError());
+    return FIF_OK;
+}
+
+// ------------------------------------------------ single-signal plain form
+
+struct SingleCache {
+    std::mutex mu;
+    struct Entry {
+        fif_plan* plan = nullptr;
+        void* ws = nullptr;
+        SigState* host_state = nullptr;
+    };
+    std::map<std::tuple<int, int64_t, int32_t, int32_t, double, int64_t, double>, Entry> map;
+    ~SingleCache() { clear(); }
+    void clear()
+    {
+        for (auto& kv : map) {
+            delete kv.second.plan;
+            if (kv.second.ws) (void)hipFree(kv.second.ws);
+            if (kv.second.host_state) (void)hipHostFree(kv.second.host_state);
+        }
+        map.clear();
+    }
+};
+SingleCache& single_cache()
+{
+    static SingleCache* c = new SingleCache();
+    return *c;
+}
+
+template <typename T>
+fif_status single(const T* x, int64_t N, fif_window window, double delta, int32_t max_imfs, T* imfs, T* rem,
+                  int32_t* n_imfs, fif_imf_info* info, const fif_options* opt_in, void* stream)
+{
+    g_err.clear();
+    if (window != FIF_WINDOW_TRI2) return fail(FIF_ERR_INVALID_ARG, "unknown window %d", (int)window);
+    if (!x || !imfs || !rem || !n_imfs) return fail(FIF_ERR_INVALID_ARG, "null buffer argument");
+    if (!(delta > 0.0) || !std::isfinite(delta)) return fail(FIF_ERR_INVALID_ARG, "delta must be > 0 and finite");
+    fif_options opt;
+    fif_options_default(&opt);
+    if (opt_in) opt = *opt_in;
+    fif_status vst = validate_opts(opt);
+    if (vst) return vst;
+    if (max_imfs < 1 || max_imfs > 4096) return fail(FIF_ERR_INVALID_ARG, "max_imfs must be in [1, 4096]");
+    if (N < 2) return fail(FIF_ERR_INVALID_ARG, "length %lld < 2", (long long)N);
+    if (!smooth7(N)) return fail(FIF_ERR_UNSUPPORTED_LENGTH, "length %lld has a prime factor > 7", (long long)N);
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    auto& C = single_cache();
+    std::lock_guard<std::mutex> lock(C.mu);
+    auto key = std::make_tuple(dev, N, max_imfs, opt.mask_rule, opt.nu, opt.max_inner, opt.floor_tau);
+    auto it = C.map.find(key);
+    if (it == C.map.end()) {
+        SingleCache::Entry e;
+        fif_status st = fif_plan_create(&e.plan, &N, 1, max_imfs, &opt);
+        if (st) return st;
+        if (hipMalloc(&e.ws, e.plan->ws_total) != hipSuccess) {
+            delete e.plan;
+            return fail(FIF_ERR_NOMEM, "workspace allocation failed");
+        }
+        if (hipHostMalloc((void**)&e.host_state, sizeof(SigState), hipHostMallocDefault) != hipSuccess) {
+            delete e.plan;
+            (void)hipFree(e.ws);
+            return fail(FIF_ERR_NOMEM, "pinned state allocation failed");
+        }
+        it = C.map.emplace(key, e).first;
+    }
+    fif_plan* p = it->second.plan;
+    SigState* hs = it->second.host_state;
+    hipStream_t s = (hipStream_t)stream;
+    Bound b = bind(p, it->second.ws, delta, info);
+    launch_init<T>(p, b, x, s);
+    for (int t = 0; t < max_imfs; ++t) {
+        launch_step<T>(p, b, t, x, imfs, s);
+        HIP_TRY(hipMemcpyAsync(hs, b.state, sizeof(SigState), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (!hs->active) {
+            // zero the rows the remaining steps would have zeroed
+            for (int u = t + 1; u < max_imfs; ++u)
+                HIP_TRY(hipMemsetAsync(imfs + (int64_t)u * N, 0, sizeof(T) * (size_t)N, s));
+            break;
+        }
+    }
+    launch_final<T>(p, b, x, rem, n_imfs, nullptr, info, s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(hs, b.state, sizeof(SigState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (hs->status != 0) return fail(FIF_ERR_NONFINITE, "signal holds NaN or Inf");
+    return FIF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fif_status fif_decompose_batched(fif_plan* plan, const float* signals, double delta, float* imfs, float* remainders,
+                                 int32_t* n_imfs, fif_imf_info* info, int32_t* sig_status, void* workspace,
+                                 void* stream)
+{
+    return batched<float>(plan, signals, delta, imfs, remainders, n_imfs, info, sig_status, workspace, stream);
+}
+
+fif_status fif_decompose_batched_f64(fif_plan* plan, const double* signals, double delta, double* imfs,
+                                     double* remainders, int32_t* n_imfs, fif_imf_info* info, int32_t* sig_status,
+                                     void* workspace, void* stream)
+{
+    return batched<double>(plan, signals, delta, imfs, remainders, n_imfs, info, sig_status, workspace, stream);
+}
+
+fif_status fif_decompose(const float* signal, int64_t N, fif_window window, double delta, int32_t max_imfs,
+                         float* imfs, float* remainder, int32_t* n_imfs, fif_imf_info* info, const fif_options* opt,
+                         void* stream)
+{
+    return single<float>(signal, N, window, delta, max_imfs, imfs, remainder, n_imfs, info, opt, stream);
+}
+
+fif_status fif_decompose_f64(const double* signal, int64_t N, fif_window window, double delta, int32_t max_imfs,
+                             double* imfs, double* remainder, int32_t* n_imfs, fif_imf_info* info,
+                             const fif_options* opt, void* stream)
+{
+    return single<double>(signal, N, window, delta, max_imfs, imfs, remainder, n_imfs, info, opt, stream);
+}
+
+fif_status fif_plan_profile(fif_plan* plan, int32_t enable)
+{
+    if (!plan) return fail(FIF_ERR_INVALID_ARG, "plan is null");
+    plan->prof = enable != 0;
+    return FIF_OK;
+}
+
+fif_status fif_plan_profile_read(fif_plan* plan, fif_kernel_time* out, int32_t cap, int32_t* n)
+{
+    if (!plan || !n || (cap > 0 && !out)) return fail(FIF_ERR_INVALID_ARG, "null argument");
+    std::vector<double> ms(plan->kinds.size(), 0.0);
+    std::vector<int64_t> cnt(plan->kinds.size(), 0);
+    hipError_t err = hipSuccess;
+    for (auto& r : plan->recs) {
+        float e = 0.f;
+        if (err == hipSuccess) err = hipEventSynchronize(r.b);
+        if (err == hipSuccess) err = hipEventElapsedTime(&e, r.a, r.b);
+        ms[r.kind] += e;
+        cnt[r.kind] += 1;
+        plan->pool.push_back(r.a);
+        plan->pool.push_back(r.b);
+    }
+    plan->recs.clear();
+    if (err != hipSuccess) return fail(FIF_ERR_DEVICE, "event timing failed: %s", hipGetErrorString(err));
+    int32_t k = 0;
+    for (size_t i = 0; i < plan->kinds.size(); ++i) {
+        if (cnt[i] == 0) continue;
+        if (k < cap) {
+            std::memset(out[k].name, 0, sizeof(out[k].name));
+            std::strncpy(out[k].name, plan->kinds[i].c_str(), sizeof(out[k].name) - 1);
+            out[k].launches = cnt[i];
+            out[k].total_ms = ms[i];
+        }
+        ++k;
+    }
+    *n = k;
+    return FIF_OK;
+}
+
+void fif_release_cache(void)
+{
+    auto& C = single_cache();
+    std::lock_guard<std::mutex> lock(C.mu);
+    C.clear();
+}
+
+}  // extern "C"

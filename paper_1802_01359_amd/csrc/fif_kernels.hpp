@@ -1,0 +1,915 @@
+// gfx950 kernels of the batched FIF hot path.
+//
+// Per outer step t (Algorithm 2, one IMF):
+//   k_scan     combine the run summaries of the residual (extrema count,
+//              min/max, at t = 0 also the sum), apply the stop rules, fix L,
+//              then pick m: FP32 exponential + bisection search on the
+//              Parseval form of SD, confirmed by FP64 sums at m and m-1;
+//   k_single / k_pass1 + k_pass2
+//              the inverse transform of z = (g + i (1 - g)) R_hat with
+//              g = (1 - lambda)^m: real part = IMF (Theorem 5 / Section 4
+//              one-step formula), imaginary part = the new residual, whose
+//              extrema are counted on the fly; R_hat <- (1 - g) R_hat.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "../../include/fif.h"
+#include "fif_fft.hpp"
+#include "fif_types.hpp"
+
+namespace fif {
+
+// ------------------------------------------------------------------ runs --
+
+__device__ __forceinline__ int sgn_step(double a, double b) { return (b > a) - (b < a); }
+
+__device__ __forceinline__ RunState run_empty()
+{
+    RunState r;
+    r.first = r.last = 0.0;
+    r.mn = INFINITY;
+    r.mx = -INFINITY;
+    r.sum = 0.0;
+    r.cnt = 0;
+    r.fs = r.ls = 0;
+    r.empty = 1;
+    r.nonfinite = 0;
+    return r;
+}
+
+__device__ __forceinline__ void run_push(RunState& r, double v)
+{
+    if (!isfinite(v)) r.nonfinite = 1;
+    if (r.empty) {
+        r.first = r.last = v;
+        r.empty = 0;
+    } else {
+        const int d = sgn_step(r.last, v);
+        if (d != 0) {
+            if (r.ls != 0 && r.ls != d) ++r.cnt;
+            if (r.fs == 0) r.fs = (int8_t)d;
+            r.ls = (int8_t)d;
+        }
+        r.last = v;
+    }
+    r.mn = fmin(r.mn, v);
+    r.mx = fmax(r.mx, v);
+    r.sum += v;
+}
+
+// a then b
+__device__ __forceinline__ RunState run_combine(const RunState& a, const RunState& b)
+{
+    if (a.empty) return b;
+    if (b.empty) return a;
+    RunState r;
+    const int d = sgn_step(a.last, b.first);
+    int cnt = a.cnt + b.cnt;
+    int x = a.ls;
+    if (d != 0) {
+        if (x != 0 && x != d) ++cnt;
+        x = d;
+    }
+    if (b.fs != 0 && x != 0 && x != b.fs) ++cnt;
+    r.fs = (int8_t)(a.fs != 0 ? a.fs : (d != 0 ? d : b.fs));
+    r.ls = (int8_t)(b.ls != 0 ? b.ls : (d != 0 ? d : a.ls));
+    r.cnt = cnt;
+    r.first = a.first;
+    r.last = b.last;
+    r.mn = fmin(a.mn, b.mn);
+    r.mx = fmax(a.mx, b.mx);
+    r.sum = a.sum + b.sum;
+    r.empty = 0;
+    r.nonfinite = a.nonfinite | b.nonfinite;
+    return r;
+}
+
+__device__ __forceinline__ RunState run_shfl_down(const RunState& r, int off)
+{
+    RunState o;
+    o.first = __shfl_down(r.first, off);
+    o.last = __shfl_down(r.last, off);
+    o.mn = __shfl_down(r.mn, off);
+    o.mx = __shfl_down(r.mx, off);
+    o.sum = __shfl_down(r.sum, off);
+    o.cnt = __shfl_down(r.cnt, off);
+    int packed = (int)(uint8_t)r.fs | ((int)(uint8_t)r.ls << 8) | ((int)r.empty << 16) |
+                 ((int)r.nonfinite << 24);
+    packed = __shfl_down(packed, off);
+    o.fs = (int8_t)(packed & 0xff);
+    o.ls = (int8_t)((packed >> 8) & 0xff);
+    o.empty = (int8_t)((packed >> 16) & 0xff);
+    o.nonfinite = (int8_t)((packed >> 24) & 0xff);
+    return o;
+}
+
+// Ordered reduction of one RunState per thread (thread order = sample
+// order).  Result valid in thread 0.  `sh` holds one RunState per wave.
+template <int NT>
+__device__ __forceinline__ RunState block_run_reduce(RunState r, RunState* sh)
+{
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        RunState o = run_shfl_down(r, off);
+        if ((lane & (2 * off - 1)) == 0) r = run_combine(r, o);
+    }
+    if (lane == 0) sh[wave] = r;
+    __syncthreads();
+    RunState tot = run_empty();
+    if (threadIdx.x == 0) {
+        for (int w = 0; w < NW; ++w) tot = run_combine(tot, sh[w]);
+    }
+    __syncthreads();
+    return tot;
+}
+
+// ------------------------------------------------------------ reductions --
+
+template <typename T, int NT>
+__device__ __forceinline__ void block_sum2(T& a, T& b, T* sh)
+{
+    constexpr int NW = NT / 64;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        a += __shfl_xor(a, off);
+        b += __shfl_xor(b, off);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        sh[2 * wave] = a;
+        sh[2 * wave + 1] = b;
+    }
+    __syncthreads();
+    T sa = 0, sb = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        sa += sh[2 * w];
+        sb += sh[2 * w + 1];
+    }
+    __syncthreads();
+    a = sa;
+    b = sb;
+}
+
+template <typename T, int NT>
+__device__ __forceinline__ void block_sum4(T* v, T* sh)
+{
+    constexpr int NW = NT / 64;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i] += __shfl_xor(v[i], off);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sh[4 * wave + i] = v[i];
+    }
+    __syncthreads();
+    T s[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) s[i] += sh[4 * w + i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = s[i];
+}
+
+// ------------------------------------------------------ window spectrum --
+
+// lambda_j = [sin(pi L j / N) / (L sin(pi j / N))]^4, the DFT of the
+// circulant column of the triangle-squared window, with L*j reduced mod N in
+// integers and both sines read from sin(pi u/N), u <= N/2.
+__device__ __forceinline__ double lambda_at(int64_t j, int64_t N, int64_t Lmod, double Ld,
+                                            const double* __restrict__ sinT)
+{
+    if (j == 0) return 1.0;
+    int64_t t = (Lmod * j) % N;
+    if (t > N - t) t = N - t;
+    const double q = sinT[t] / (Ld * sinT[j]);
+    const double q2 = q * q;
+    return q2 * q2;
+}
+
+// (1 - lambda)^m
+__device__ __forceinline__ double gain_pow(double lam, int64_t m)
+{
+    if (lam >= 1.0) return 0.0;
+    return exp((double)m * log1p(-lam));
+}
+
+// --------------------------------------------------------------- tables --
+
+__global__ void k_fill_sin(double* __restrict__ out, int64_t N, int64_t count)
+{
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u < count) out[u] = sinpi((double)u / (double)N);
+}
+
+// exp(-2 pi i k / den) for k < count, written at out[k]
+__global__ void k_fill_roots(double2* __restrict__ out, int64_t den, int64_t count, int64_t stride)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < count) {
+        double s, c;
+        sincospi(2.0 * (double)(k * stride) / (double)den, &s, &c);
+        out[k] = make_double2(c, -s);
+    }
+}
+
+// four-step twiddle exp(-+2 pi i a / N), a < N, from the split tables
+template <bool INV>
+__device__ __forceinline__ double2 big_twiddle(const LenPlan& lp, const double2* __restrict__ tabs, int64_t a)
+{
+    double2 w = cmul(tabs[lp.big_hi_off + a / lp.big_split], tabs[lp.big_lo_off + a % lp.big_split]);
+    if (INV) w.y = -w.y;
+    return w;
+}
+
+// ------------------------------------------------------- init statistics --
+
+// Run summary of one tile of the input signal (first outer step's count,
+// min/max, sum and non-finite check).
+template <typename InT>
+__global__ __launch_bounds__(kFftThreads) void k_init_stats(const SigDesc* __restrict__ sigs,
+                                                             const Work* __restrict__ work,
+                                                             const InT* __restrict__ x,
+                                                             RunState* __restrict__ parts)
+{
+    __shared__ RunState sh[kFftThreads / 64];
+    const Work w = work[blockIdx.x];
+    const SigDesc d = sigs[w.sig];
+    const int64_t t0 = (int64_t)w.tile * kFftCap;
+    const int64_t len = min((int64_t)kFftCap, d.N - t0);
+    const int chunk = (int)((len + kFftThreads - 1) / kFftThreads);
+    const int64_t a = (int64_t)threadIdx.x * chunk, b = min(len, a + chunk);
+    RunState r = run_empty();
+    for (int64_t i = a; i < b; ++i) run_push(r, (double)x[d.off + t0 + i]);
+    r = block_run_reduce<kFftThreads>(r, sh);
+    if (threadIdx.x == 0) parts[d.part_off + w.tile] = r;
+}
+
+// ------------------------------------------------------ transform modes --
+
+enum Mode { MODE_FORWARD = 0, MODE_STEP = 1, MODE_REMAINDER = 2 };
+
+struct StepArgs {
+    const SigDesc* sigs;
+    const LenPlan* lens;
+    const Work* work;
+    SigState* st;
+    const double* dtab;    // sine tables
+    const double2* ctab;   // twiddle tables
+    double2* spec0;
+    double2* spec1;
+    double2* inter;
+    RunState* parts;
+    int t;                 // outer step (MODE_STEP)
+    int max_imfs;
+};
+
+// Spectrum buffer index read by outer step t.
+__device__ __forceinline__ double2* spec_in(const StepArgs& A, int buf) { return buf ? A.spec1 : A.spec0; }
+
+// Element z_k of the inverse-transform input for k in [0, N): bin
+// j = min(k, N-k) of the current residual spectrum (conjugated for k > N/2)
+// times (g_j + i (1 - g_j)) / N.
+__device__ __forceinline__ double2 step_input(double2 v, bool mirror, double g, double invN)
+{
+    const double h = 1.0 - g;
+    if (mirror) v.y = -v.y;
+    return make_double2((g * v.x - h * v.y) * invN, (g * v.y + h * v.x) * invN);
+}
+
+// -------------------------------------------------- single LDS pass (N <= cap)
+
+// One workgroup per signal.  FORWARD: real input -> half spectrum (buffer 0)
+// and nothing else.  STEP: apply, inverse transform, IMF row t, run summary of
+// the residual, next spectrum.  REMAINDER: inverse transform of the final
+// spectrum, imaginary part only.
+template <int MODE, typename InT, typename OutT>
+__global__ __launch_bounds__(kFftThreads) void k_single(StepArgs A, const InT* __restrict__ x,
+                                                        OutT* __restrict__ imfs, OutT* __restrict__ rem)
+{
+    extern __shared__ double2 lds[];
+    __shared__ RunState sh[kFftThreads / 64];
+    const Work w = A.work[blockIdx.x];
+    const SigDesc d = A.sigs[w.sig];
+    const LenPlan& lp = A.lens[d.len_id];
+    const int N = (int)d.N;
+    const int nh = N / 2;
+    SigState* S = A.st + w.sig;
+
+    if (MODE == MODE_FORWARD) {
+        for (int k = threadIdx.x; k < N; k += kFftThreads) lds[k] = make_double2((double)x[d.off + k], 0.0);
+        __syncthreads();
+        lds_fft<false>(lds, lp.f1, 1, A.ctab);
+        double2* out = A.spec0 + d.spec_off;
+        for (int k = threadIdx.x; k <= nh; k += kFftThreads) out[k] = lds[k];
+        return;
+    }
+    if (MODE == MODE_REMAINDER && S->status != 0) {
+        for (int k = threadIdx.x; k < N; k += kFftThreads) rem[d.off + k] = (OutT)x[d.off + k];
+        return;
+    }
+    if (MODE == MODE_STEP && !S->active) {
+        OutT* row = imfs + (int64_t)A.max_imfs * d.off + (int64_t)A.t * N;
+        for (int k = threadIdx.x; k < N; k += kFftThreads) row[k] = (OutT)0;
+        return;
+    }
+    const int buf = (MODE == MODE_STEP) ? (A.t & 1) : S->final_buf;
+    const double2* Rin = spec_in(A, buf) + d.spec_off;
+    double2* Rout = spec_in(A, buf ^ 1) + d.spec_off;
+    const double invN = 1.0 / (double)N;
+    const int64_t L = S->L, m = S->m;
+    const int64_t Lmod = L % N;
+    const double* sinT = A.dtab + lp.sin_off;
+    for (int j = threadIdx.x; j <= nh; j += kFftThreads) {
+        const double2 v = Rin[j];
+        double g = 0.0;
+        if (MODE == MODE_STEP) g = gain_pow(lambda_at(j, N, Lmod, (double)L, sinT), m);
+        lds[j] = step_input(v, false, g, invN);
+        if (j != 0 && 2 * j != N) lds[N - j] = step_input(v, true, g, invN);
+        if (MODE == MODE_STEP) Rout[j] = cscale(v, 1.0 - g);
+    }
+    __syncthreads();
+    lds_fft<true>(lds, lp.f1, 1, A.ctab);
+    if (MODE == MODE_REMAINDER) {
+        for (int k = threadIdx.x; k < N; k += kFftThreads) rem[d.off + k] = (OutT)lds[k].y;
+        return;
+    }
+    OutT* row = imfs + (int64_t)A.max_imfs * d.off + (int64_t)A.t * N;
+    for (int k = threadIdx.x; k < N; k += kFftThreads) row[k] = (OutT)lds[k].x;
+    const int chunk = (N + kFftThreads - 1) / kFftThreads;
+    const int a = threadIdx.x * chunk, b = min(N, a + chunk);
+    RunState r = run_empty();
+    for (int i = a; i < b; ++i) run_push(r, lds[i].y);
+    r = block_run_reduce<kFftThreads>(r, sh);
+    if (threadIdx.x == 0) A.parts[d.part_off] = r;
+}
+
+// ----------------------------------------------- four-step pass 1 (columns)
+
+// Work tile = TC consecutive columns c of the N2 x N1 view (element index
+// c + N1 * r).  Transforms each column over r (length N2), multiplies by the
+// four-step twiddle of (r', c) and writes Y[r'][c] to the intermediate.
+template <int MODE, typename InT>
+__global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __restrict__ x)
+{
+    extern __shared__ double2 lds[];
+    const Work w = A.work[blockIdx.x];
+    const SigDesc d = A.sigs[w.sig];
+    const LenPlan& lp = A.lens[d.len_id];
+    const int64_t N = d.N;
+    const int N1 = lp.N1, N2 = lp.N2, TC = lp.TC;
+    const int c0 = w.tile * TC;
+    SigState* S = A.st + w.sig;
+    if (MODE == MODE_STEP && !S->active) return;
+    if (MODE == MODE_REMAINDER && S->status != 0) return;
+    const int total = TC * N2;
+    if (MODE == MODE_FORWARD) {
+        for (int f = threadIdx.x; f < total; f += kFftThreads) {
+            const int cl = f % TC, r = f / TC;
+            lds[f] = make_double2((double)x[d.off + c0 + cl + (int64_t)N1 * r], 0.0);
+        }
+    } else {
+        const int buf = (MODE == MODE_STEP) ? (A.t & 1) : S->final_buf;
+        const double2* Rin = spec_in(A, buf) + d.spec_off;
+        double2* Rout = spec_in(A, buf ^ 1) + d.spec_off;
+        const double invN = 1.0 / (double)N;
+        const int64_t L = S->L, m = S->m;
+        const int64_t Lmod = L % N;
+        const double* sinT = A.dtab + lp.sin_off;
+        const int64_t nh = N / 2;
+        for (int f = threadIdx.x; f < total; f += kFftThreads) {
+            const int cl = f % TC, r = f / TC;
+            const int64_t k = c0 + cl + (int64_t)N1 * r;
+            const bool mirror = k > nh;
+            const int64_t j = mirror ? N - k : k;
+            const double2 v = Rin[j];
+            double g = 0.0;
+            if (MODE == MODE_STEP) g = gain_pow(lambda_at(j, N, Lmod, (double)L, sinT), m);
+            lds[f] = step_input(v, mirror, g, invN);
+            if (MODE == MODE_STEP && !mirror) Rout[j] = cscale(v, 1.0 - g);
+        }
+    }
+    __syncthreads();
+    if (MODE == MODE_FORWARD)
+        lds_fft<false>(lds, lp.f1, TC, A.ctab);
+    else
+        lds_fft<true>(lds, lp.f1, TC, A.ctab);
+    double2* Y = A.inter + d.inter_off;
+    for (int f = threadIdx.x; f < total; f += kFftThreads) {
+        const int cl = f % TC, rp = f / TC;
+        const int c = c0 + cl;
+        const int64_t a = (int64_t)rp * c;
+        double2 v = lds[f];
+        if (a != 0) {
+            const double2 tw = (MODE == MODE_FORWARD) ? big_twiddle<false>(lp, A.ctab, a)
+                                                      : big_twiddle<true>(lp, A.ctab, a);
+            v = cmul(v, tw);
+        }
+        Y[(int64_t)rp * N1 + c] = v;
+    }
+}
+
+// -------------------------------------------------- four-step pass 2 (rows)
+
+// Work tile = TR consecutive rows r' of Y.  Transforms each row over c
+// (length N1); output element N2 * c' + r'.  STEP: IMF and one run summary
+// per c' (TR consecutive samples); FORWARD: half spectrum; REMAINDER: y.
+template <int MODE, typename InT, typename OutT>
+__global__ __launch_bounds__(kFftThreads) void k_pass2(StepArgs A, const InT* __restrict__ x,
+                                                       OutT* __restrict__ imfs, OutT* __restrict__ rem)
+{
+    extern __shared__ double2 lds[];
+    const Work w = A.work[blockIdx.x];
+    const SigDesc d = A.sigs[w.sig];
+    const LenPlan& lp = A.lens[d.len_id];
+    const int64_t N = d.N;
+    const int N1 = lp.N1, N2 = lp.N2, TR = lp.TR;
+    const int r0 = w.tile * TR;
+    SigState* S = A.st + w.sig;
+    const int total = TR * N1;
+    if (MODE == MODE_STEP && !S->active) {
+        OutT* row = imfs + (int64_t)A.max_imfs * d.off + (int64_t)A.t * N;
+        for (int f = threadIdx.x; f < total; f += kFftThreads) {
+            const int cp = f / TR, rl = f % TR;
+            row[(int64_t)N2 * cp + r0 + rl] = (OutT)0;
+        }
+        return;
+    }
+    if (MODE == MODE_REMAINDER && S->status != 0) {
+        for (int f = threadIdx.x; f < total; f += kFftThreads) {
+            const int cp = f / TR, rl = f % TR;
+            const int64_t n = (int64_t)N2 * cp + r0 + rl;
+            rem[d.off + n] = (OutT)x[d.off + n];
+        }
+        return;
+    }
+    const double2* Y = A.inter + d.inter_off;
+    for (int f = threadIdx.x; f < total; f += kFftThreads) {
+        const int rl = f / N1, c = f % N1;
+        lds[c * TR + rl] = Y[(int64_t)(r0 + rl) * N1 + c];
+    }
+    __syncthreads();
+    if (MODE == MODE_FORWARD)
+        lds_fft<false>(lds, lp.f2, TR, A.ctab);
+    else
+        lds_fft<true>(lds, lp.f2, TR, A.ctab);
+    if (MODE == MODE_FORWARD) {
+        double2* out = A.spec0 + d.spec_off;
+        const int64_t nh = N / 2;
+        for (int f = threadIdx.x; f < total; f += kFftThreads) {
+            const int cp = f / TR, rl = f % TR;
+            const int64_t n = (int64_t)N2 * cp + r0 + rl;
+            if (n <= nh) out[n] = lds[f];
+        }
+        return;
+    }
+    if (MODE == MODE_REMAINDER) {
+        for (int f = threadIdx.x; f < total; f += kFftThreads) {
+            const int cp = f / TR, rl = f % TR;
+            rem[d.off + (int64_t)N2 * cp + r0 + rl] = (OutT)lds[f].y;
+        }
+        return;
+    }
+    OutT* row = imfs + (int64_t)A.max_imfs * d.off + (int64_t)A.t * N;
+    for (int f = threadIdx.x; f < total; f += kFftThreads) {
+        const int cp = f / TR, rl = f % TR;
+        row[(int64_t)N2 * cp + r0 + rl] = (OutT)lds[f].x;
+    }
+    const int runs_per_row = N2 / TR;
+    for (int cp = threadIdx.x; cp < N1; cp += kFftThreads) {
+        RunState r = run_empty();
+        for (int rl = 0; rl < TR; ++rl) run_push(r, lds[cp * TR + rl].y);
+        A.parts[d.part_off + cp * runs_per_row + w.tile] = r;
+    }
+}
+
+// ------------------------------------------------------------------- scan --
+
+struct ScanArgs {
+    const SigDesc* sigs;
+    const LenPlan* lens;
+    const int32_t* list;      // signal handled by each workgroup
+    SigState* st;
+    const RunState* parts;
+    const double* dtab;
+    const double2* spec0;
+    const double2* spec1;
+    float* gscr;              // per-signal FP32 scratch for N > register capacity
+    const int64_t* gscr_off;  // per-signal offset into gscr (floats), -1 if unused
+    fif_imf_info* info;       // [B][max_imfs] or null
+    int t;
+    int max_imfs;
+    double delta;
+    int mask_rule;
+    double nu;
+    int64_t max_inner;
+    double floor_tau;
+};
+
+__device__ __forceinline__ int64_t mask_length(int64_t N, int64_t k, int rule, double nu)
+{
+    if (rule == 0) return (2 * N + k - 1) / k;
+    const int64_t L = 2 * (int64_t)floor(nu * (double)N / (double)k);
+    return L < 1 ? 1 : L;
+}
+
+// Per-thread bins j = 1 + tid + i*T, i < BPT (fast path: tau and b in
+// registers, a in LDS at [i*T + tid]) -- or all bins via global scratch when
+// BPT == 0.
+template <int BPT>
+struct ScanBins {
+    float tau[BPT > 0 ? BPT : 1], b[BPT > 0 ? BPT : 1];
+};
+
+// One workgroup per signal.
+template <int BPT>
+__global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
+{
+    constexpr int T = kScanThreads;
+    __shared__ RunState shr[T / 64];
+    __shared__ double shd[4 * (T / 64)];
+    __shared__ float shf[2 * (T / 64)];
+    __shared__ int64_t sh_i[4];
+    __shared__ double sh_pscale;
+
+    const int s = A.list[blockIdx.x];
+    const SigDesc d = A.sigs[s];
+    SigState* S = A.st + s;
+    if (!S->active) return;
+    const LenPlan& lp = A.lens[d.len_id];
+    const int64_t N = d.N;
+    const int tid = threadIdx.x;
+
+    // ---- combine run summaries of the residual (sample order) ----
+    {
+        const int n = (A.t == 0) ? d.n_init_parts : d.n_parts;
+        const RunState* P = A.parts + d.part_off;
+        const int chunk = (n + T - 1) / T;
+        const int a = tid * chunk, b = min(n, a + chunk);
+        RunState r = run_empty();
+        for (int i = a; i < b; ++i) r = run_combine(r, P[i]);
+        r = block_run_reduce<T>(r, shr);
+        if (tid == 0) {
+            int stop = -1;
+            if (A.t == 0) {
+                if (r.nonfinite) {
+                    S->status = FIF_ERR_NONFINITE;
+                    stop = FIF_STOP_FAILED;
+                } else {
+                    S->mean = r.sum / (double)N;
+                    S->maxabs = fmax(fabs(r.mn), fabs(r.mx));
+                    // power-of-two scale keeping the FP32 powers below 1
+                    const double top = (double)N * S->maxabs;
+                    S->pscale = top > 0.0 ? ldexp(1.0, -2 * (ilogb(top) + 1)) : 1.0;
+                }
+            }
+            if (stop < 0) {
+                const double dev = fmax(r.mx - S->mean, S->mean - r.mn);
+                if (dev <= A.floor_tau * S->maxabs)
+                    stop = FIF_STOP_FLOOR;
+                else if (r.cnt < 2)
+                    stop = FIF_STOP_FEW_EXTREMA;
+            }
+            if (stop >= 0) {
+                S->active = 0;
+                S->stop_reason = stop;
+                S->n_imfs = A.t;
+                S->final_buf = A.t & 1;
+                sh_i[0] = -1;
+            } else {
+                S->k = r.cnt;
+                sh_i[0] = mask_length(N, r.cnt, A.mask_rule, A.nu);
+            }
+            sh_pscale = S->pscale;
+        }
+        __syncthreads();
+    }
+    const int64_t L = sh_i[0];
+    if (L < 0) return;
+
+    const int64_t nh = N / 2;
+    const int64_t Lmod = L % N;
+    const double Ld = (double)L;
+    const double* sinT = A.dtab + lp.sin_off;
+    const double2* R = ((A.t & 1) ? A.spec1 : A.spec0) + d.spec_off;
+    const double pscale = sh_pscale;
+    const double delta = A.delta;
+    const float d2f = (float)(delta * delta);
+    const int64_t cap = A.max_inner;
+
+    // ---- first sweep: FP32 copies of the weighted power, power*lambda^2,
+    //      log2 of mu = (1 - lambda)^2 (DC kept aside: lambda_0 = 1) ----
+    ScanBins<BPT> bins;
+    extern __shared__ float lds_a[];
+    float* gs = (BPT == 0) ? (A.gscr + A.gscr_off[s]) : nullptr;
+    const int64_t nb = nh;  // bins 1..nh
+    auto weight = [&](int64_t j) -> double { return (2 * j == N) ? 1.0 : 2.0; };
+    auto sweep_bin = [&](int64_t j, float& tau, float& av, float& bv) {
+        const double2 v = R[j];
+        const double P = weight(j) * (v.x * v.x + v.y * v.y) * pscale;
+        const double lam = lambda_at(j, N, Lmod, Ld, sinT);
+        bv = (float)P;
+        av = (float)(P * lam * lam);
+        tau = (float)(2.0 * log1p(-lam) * 1.4426950408889634);
+    };
+    if (BPT > 0) {
+#pragma unroll
+        for (int i = 0; i < (BPT > 0 ? BPT : 1); ++i) {
+            const int64_t j = 1 + tid + (int64_t)i * T;
+            float av = 0.f;
+            if (j <= nb) {
+                sweep_bin(j, bins.tau[i], av, bins.b[i]);
+            } else {
+                bins.tau[i] = 0.f;
+                bins.b[i] = 0.f;
+            }
+            lds_a[i * T + tid] = av;
+        }
+    } else {
+        for (int64_t j = 1 + tid; j <= nb; j += T) {
+            float tau, av, bv;
+            sweep_bin(j, tau, av, bv);
+            gs[3 * (j - 1)] = tau;
+            gs[3 * (j - 1) + 1] = av;
+            gs[3 * (j - 1) + 2] = bv;
+        }
+    }
+    const double P0 = (R[0].x * R[0].x + R[0].y * R[0].y) * pscale;
+    __syncthreads();
+
+    // SD_m <= delta in FP32: A(m) = sum a x, B(m) = sum b x, x = mu^(m-1)
+    auto ok32 = [&](int64_t m) -> bool {
+        float sa = 0.f, sb = 0.f;
+        const float c = (float)(m - 1);
+        if (m == 1) {
+            if (BPT > 0) {
+#pragma unroll
+                for (int i = 0; i < (BPT > 0 ? BPT : 1); ++i) {
+                    sa += lds_a[i * T + tid];
+                    sb += bins.b[i];
+                }
+            } else {
+                for (int64_t j = 1 + tid; j <= nb; j += T) {
+                    sa += gs[3 * (j - 1) + 1];
+                    sb += gs[3 * (j - 1) + 2];
+                }
+            }
+            if (tid == 0) {
+                sa += (float)P0;
+                sb += (float)P0;
+            }
+        } else {
+            if (BPT > 0) {
+#pragma unroll
+                for (int i = 0; i < (BPT > 0 ? BPT : 1); ++i) {
+                    const float xx = exp2f(c * bins.tau[i]);
+                    sa += lds_a[i * T + tid] * xx;
+                    sb += bins.b[i] * xx;
+                }
+            } else {
+                for (int64_t j = 1 + tid; j <= nb; j += T) {
+                    const float xx = exp2f(c * gs[3 * (j - 1)]);
+                    sa += gs[3 * (j - 1) + 1] * xx;
+                    sb += gs[3 * (j - 1) + 2] * xx;
+                }
+            }
+        }
+        block_sum2<float, T>(sa, sb, shf);
+        return sb == 0.f || sa <= d2f * sb;
+    };
+
+    // FP64 SD at exponents e and e+1 of mu (m = e+1 and e+2)
+    auto sd64 = [&](int64_t m, double& sd_m, double& sd_mm1) {
+        // sums at m-1 (index 0,1) and m (index 2,3); e = m - 2 may be -1
+        double v[4] = {0.0, 0.0, 0.0, 0.0};
+        const int64_t e = m - 2;
+        for (int64_t j = 1 + tid; j <= nb; j += T) {
+            const double2 z = R[j];
+            const double P = weight(j) * (z.x * z.x + z.y * z.y) * pscale;
+            const double lam = lambda_at(j, N, Lmod, Ld, sinT);
+            const double l2 = lam * lam;
+            const double lg = 2.0 * log1p(-lam);  // log mu
+            const double xm = (lam >= 1.0) ? 0.0 : exp((double)(m - 1) * lg);
+            if (e >= 0) {
+                const double xe = (lam >= 1.0) ? (e == 0 ? 1.0 : 0.0) : exp((double)e * lg);
+                v[0] += P * l2 * xe;
+                v[1] += P * xe;
+            }
+            v[2] += P * l2 * xm;
+            v[3] += P * xm;
+        }
+        if (tid == 0) {
+            if (m == 1) {
+                v[2] += P0;
+                v[3] += P0;
+            }
+            if (m == 2) {
+                v[0] += P0;
+                v[1] += P0;
+            }
+        }
+        block_sum4<double, T>(v, shd);
+        sd_m = v[3] > 0.0 ? sqrt(v[2] / v[3]) : 0.0;
+        sd_mm1 = (m == 1) ? INFINITY : (v[1] > 0.0 ? sqrt(v[0] / v[1]) : 0.0);
+    };
+
+    // ---- FP32 exponential search + bisection for the smallest m with
+    //      SD <= delta (SD is non-increasing in m); mt = cap if none is found
+    int64_t mt;
+    {
+        int64_t lo = 0, hi = -1, step = 1, cand = 1;
+        while (true) {
+            const bool ok = ok32(cand);
+            if (hi < 0) {
+                if (ok) {
+                    hi = cand;
+                } else {
+                    lo = cand;
+                    if (cand >= cap) {
+                        hi = cap;
+                        break;
+                    }
+                    cand = min(cap, lo + step);
+                    step *= 2;
+                    continue;
+                }
+            } else if (ok) {
+                hi = cand;
+            } else {
+                lo = cand;
+            }
+            if (hi - lo <= 1) break;
+            cand = lo + (hi - lo) / 2;
+        }
+        mt = hi;
+    }
+
+    // ---- FP64 confirmation of mt (SD_mt <= delta < SD_{mt-1}); otherwise an
+    //      exact FP64 gallop + bisection from mt, then a final evaluation
+    uint32_t flags = 0;
+    int64_t m = mt;
+    double sd_m = 0.0, sd_p = 0.0;
+    {
+        // stage 0 confirm, 1 gallop up, 2 gallop down, 3 bisect, 4 final
+        int stage = 0;
+        int64_t cand = mt, elo = 0, ehi = -1, gstep = 1;
+        while (true) {
+            double sm, sp;
+            sd64(cand, sm, sp);
+            const bool okm = sm <= delta;
+            if (stage == 4) {
+                sd_m = sm;
+                sd_p = sp;
+                break;
+            }
+            if (stage == 0) {
+                const bool okp = sp <= delta;
+                if (okm && !okp) {
+                    m = cand;
+                    sd_m = sm;
+                    sd_p = sp;
+                    break;
+                }
+                flags |= FIF_IMF_REFINED;
+                if (!okm) {
+                    if (cand >= cap) {
+                        m = cap;
+                        sd_m = sm;
+                        sd_p = sp;
+                        break;
+                    }
+                    elo = cand;
+                    stage = 1;
+                } else {
+                    ehi = cand - 1;  // SD_{cand-1} <= delta
+                    stage = 2;
+                }
+            } else if (stage == 1) {
+                if (okm) {
+                    ehi = cand;
+                    stage = 3;
+                } else {
+                    elo = cand;
+                    if (cand >= cap) {
+                        m = cap;
+                        sd_m = sm;
+                        sd_p = sp;
+                        break;
+                    }
+                }
+            } else if (stage == 2) {
+                if (okm) {
+                    ehi = cand;
+                } else {
+                    elo = cand;
+                    stage = 3;
+                }
+            } else {
+                if (okm)
+                    ehi = cand;
+                else
+                    elo = cand;
+            }
+            // next candidate
+            if (stage == 1) {
+                cand = min(cap, elo + gstep);
+                gstep *= 2;
+            } else if (stage == 2) {
+                if (ehi <= 1) {
+                    elo = 0;
+                    stage = 3;
+                } else {
+                    cand = max((int64_t)1, ehi - gstep);
+                    gstep *= 2;
+                }
+            }
+            if (stage == 3) {
+                if (ehi - elo <= 1) {
+                    m = ehi;
+                    cand = ehi;
+                    stage = 4;
+                } else {
+                    cand = elo + (ehi - elo) / 2;
+                }
+            }
+        }
+    }
+    if (sd_m > delta) flags |= FIF_IMF_CAP;
+
+    if (tid == 0) {
+        S->L = L;
+        S->m = m;
+        S->sd = sd_m;
+        S->sd_prev = sd_p;
+        S->flags |= (int32_t)flags;
+        if (A.info) {
+            fif_imf_info* I = A.info + (int64_t)s * A.max_imfs + A.t;
+            I->k = S->k;
+            I->L = L;
+            I->m = m;
+            I->sd = sd_m;
+            I->sd_prev = sd_p;
+            I->flags = flags;
+            I->reserved = 0;
+        }
+    }
+}
+
+// ------------------------------------------------------------- finalize --
+
+__global__ void k_finalize(SigState* __restrict__ st, int B, int max_imfs, int32_t* __restrict__ n_imfs,
+                           int32_t* __restrict__ sig_status, fif_imf_info* __restrict__ info)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= B) return;
+    SigState* S = st + s;
+    if (S->active) {
+        S->active = 0;
+        S->n_imfs = max_imfs;
+        S->stop_reason = FIF_STOP_MAX_IMFS;
+        S->final_buf = max_imfs & 1;
+    }
+    if (n_imfs) n_imfs[s] = S->n_imfs;
+    if (sig_status) sig_status[s] = S->status;
+    if (info) {
+        for (int j = S->n_imfs; j < max_imfs; ++j) {
+            fif_imf_info* I = info + (int64_t)s * max_imfs + j;
+            I->k = 0;
+            I->L = 0;
+            I->m = 0;
+            I->sd = 0.0;
+            I->sd_prev = 0.0;
+            I->flags = 0;
+            I->reserved = 0;
+        }
+    }
+}
+
+__global__ void k_reset_state(SigState* __restrict__ st, int B)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= B) return;
+    SigState z;
+    z.k = z.L = z.m = 0;
+    z.sd = z.sd_prev = 0.0;
+    z.mean = z.maxabs = 0.0;
+    z.pscale = 1.0;
+    z.active = 1;
+    z.n_imfs = 0;
+    z.stop_reason = 0;
+    z.status = 0;
+    z.final_buf = 0;
+    z.flags = 0;
+    st[s] = z;
+}
+
+}  // namespace fif

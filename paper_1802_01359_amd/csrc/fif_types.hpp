@@ -1,0 +1,77 @@
+// Descriptors shared by the host runtime and the gfx950 kernels of libfif.
+#pragma once
+#include <stdint.h>
+
+namespace fif {
+
+// Largest complex FP64 FFT held in one workgroup's LDS (128 KiB).
+constexpr int kFftCap = 8192;
+// Threads of the FFT workgroups and of the scan workgroups.
+constexpr int kFftThreads = 512;
+constexpr int kScanThreads = 1024;
+// Spectrum bins a scan thread keeps in registers (fast path: N <= 65536).
+constexpr int kScanBinsPerThread = 32;
+constexpr int kMaxRadices = 24;
+
+// Radix plan of one LDS-resident complex FFT of length n.
+struct SubFft {
+    int32_t n;
+    int32_t nrad;
+    int32_t tw_off;                // offset (complex elements) of its pass twiddles
+    int8_t rad[kMaxRadices];
+};
+
+// Per distinct signal length.
+struct LenPlan {
+    int64_t N;
+    int32_t two_pass;              // 0: single LDS pass; 1: N = N1 * N2 four-step
+    int32_t N1, N2;                // N1: pass-2 length (columns), N2: pass-1 length (rows)
+    int32_t TC, TR;                // pass-1 column tile, pass-2 row tile
+    SubFft f1;                     // length N2 (pass 1) or N (single pass)
+    SubFft f2;                     // length N1 (pass 2)
+    int64_t sin_off;               // offset (doubles) of sin(pi u/N), u = 0..N/2
+    int64_t big_lo_off, big_hi_off;// offsets (complex) of the four-step twiddle tables
+    int32_t big_split;             // exp(-2 pi i a/N) = hi[a / split] * lo[a % split]
+    int32_t pad;
+};
+
+// Per signal of the batch.
+struct SigDesc {
+    int64_t N;
+    int64_t off;                   // element offset in packed signals/remainders
+    int64_t spec_off;              // complex offset of its half spectrum (N/2+1 bins)
+    int64_t inter_off;             // complex offset of its four-step intermediate
+    int32_t len_id;
+    int32_t part_off;              // offset of its run partials
+    int32_t n_parts;               // run partials written per outer step
+    int32_t n_init_parts;          // run partials written by the init statistics
+};
+
+// Ordered summary of a run of consecutive samples: enough to count sign
+// changes of nonzero forward differences across runs, plus min/max/sum.
+struct RunState {
+    double first, last, mn, mx, sum;
+    int32_t cnt;
+    int8_t fs, ls, empty, nonfinite;
+};
+
+// Mutable per-signal state in the workspace.
+struct SigState {
+    int64_t k, L, m;
+    double sd, sd_prev;
+    double mean, maxabs, pscale;
+    int32_t active;                // 1 while the outer loop runs
+    int32_t n_imfs;
+    int32_t stop_reason;
+    int32_t status;                // 0 or FIF_ERR_NONFINITE
+    int32_t final_buf;             // spectrum buffer holding the final residual
+    int32_t flags;
+};
+
+// Work item of the FFT kernels: signal and tile index.
+struct Work {
+    int32_t sig;
+    int32_t tile;
+};
+
+}  // namespace fif

@@ -1,0 +1,256 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Decisions (extrema count k, mask length L, step count m, number of IMFs)
+must be identical; a mismatch is tolerated only as a certified tie, i.e.
+when the oracle's own margin shows the decision sits within rounding of the
+threshold.  IMFs: FP64 entry points within ||d|| <= 1e-12 ||IMF|| +
+1e-15 ||s||; FP32 entry points within 1e-5 relative L2 per IMF.
+"""
+from __future__ import annotations
+
+import math
+import os
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+import siggen
+from oracle import dif
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1802_01359_amd as fif  # noqa: E402
+
+TIE = 1e-10
+
+
+def oracle_many(signals, delta, max_imfs, **kw):
+    """Oracle decompositions in parallel threads (the C oracle releases the GIL)."""
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        futs = [ex.submit(dif.decompose, s, delta, max_imfs, **kw) for s in signals]
+        return [f.result() for f in futs]
+
+
+def _decisions_match(ref, info, n):
+    """Decisions equal, or the first difference is a certified tie."""
+    if n != ref.n_imfs:
+        j = min(n, ref.n_imfs)
+    else:
+        j = None
+        for i in range(n):
+            if (int(info["k"][i]), int(info["L"][i]), int(info["m"][i])) != (ref.k[i], ref.L[i], ref.m[i]):
+                j = i
+                break
+        if j is None:
+            return True, None
+    # certified tie: the oracle's count margin or its SD margin at the split
+    if j < ref.n_imfs:
+        if ref.margin_k[j] < TIE:
+            return False, j
+        for sd in (ref.sd[j], ref.sd_prev[j]):
+            if math.isfinite(sd) and abs(sd / ref_delta[0] - 1.0) < TIE:
+                return False, j
+    raise AssertionError("decision mismatch at IMF %d: gpu n=%d %s vs oracle n=%d %s" % (
+        j, n, list(zip(info["k"][:n], info["L"][:n], info["m"][:n])), ref.n_imfs,
+        list(zip(ref.k, ref.L, ref.m))))
+
+
+ref_delta = [1e-3]
+
+
+def _check(ref, s, imfs, rem, info, n, delta, fp64):
+    ref_delta[0] = delta
+    same, tie_at = _decisions_match(ref, info, n)
+    upto = n if same else tie_at
+    sn = np.linalg.norm(s)
+    for j in range(upto):
+        a, b = ref.imfs[j], imfs[j]
+        err = np.linalg.norm(a - b)
+        if fp64:
+            assert err <= 1e-12 * np.linalg.norm(a) + 1e-15 * sn, (j, err, np.linalg.norm(a))
+        else:
+            assert err <= 1e-5 * np.linalg.norm(a) + 1e-30, (j, err / max(np.linalg.norm(a), 1e-300))
+    if same:
+        err = np.linalg.norm(ref.remainder - rem)
+        if fp64:
+            assert err <= 1e-12 * np.linalg.norm(ref.remainder) + 1e-15 * sn
+        else:
+            assert err <= 1e-5 * np.linalg.norm(ref.remainder) + 1e-7 * sn
+        assert np.all(imfs[n:] == 0)
+
+
+def _signal(N, seed):
+    if N < 64:
+        return np.random.default_rng(seed).standard_normal(N)
+    f = (max(1.0, N / 700.0), max(2.0, N / 90.0), N / 9.0)
+    return siggen.tones3(N=N, freqs=f, seed_index=seed)
+
+
+@pytest.mark.parametrize("N", [2, 3, 8, 30, 105, 360, 1000, 2048, 4096, 6000, 8192,
+                               10000, 16384, 20736, 65536])
+def test_fp64_single_matches_oracle(N):
+    s = _signal(N, N)
+    max_imfs = 6
+    ref = dif.decompose(s, 1e-3, max_imfs)
+    x = torch.tensor(s, dtype=torch.float64, device="cuda")
+    print("case fp64 single N=%d" % N, flush=True)
+    res = fif.decompose(x, 1e-3, max_imfs)
+    torch.cuda.synchronize()
+    imfs = np.zeros((max_imfs, N))
+    imfs[:res.n_imfs] = res.imfs.cpu().numpy()
+    _check(ref, s, imfs, res.remainder.cpu().numpy(), res.info, res.n_imfs, 1e-3, True)
+
+
+def test_three_tone_workload_fp64():
+    """N = 4096, three AM tones at 8/40/200 cycles, delta 1e-3, 8 IMFs."""
+    s = siggen.tones3()
+    ref = dif.decompose(s, 1e-3, 8)
+    x = torch.tensor(s, dtype=torch.float64, device="cuda")
+    res = fif.decompose(x, 1e-3, 8)
+    torch.cuda.synchronize()
+    assert list(res.info["k"]) == [401, 79, 16, 6, 4]
+    assert list(res.info["m"]) == ref.m
+    imfs = np.zeros((8, 4096))
+    imfs[:res.n_imfs] = res.imfs.cpu().numpy()
+    _check(ref, s, imfs, res.remainder.cpu().numpy(), res.info, res.n_imfs, 1e-3, True)
+
+
+def _run_batch(lengths, sigs, delta, max_imfs, dtype, **opt):
+    plan = fif.Plan(lengths, max_imfs, fif.Options(**opt))
+    packed = torch.tensor(np.concatenate(sigs), dtype=dtype, device="cuda")
+    out = plan.run(packed, delta)
+    torch.cuda.synchronize()
+    return plan, packed, out
+
+
+@pytest.mark.parametrize("delta,lengths", [
+    (1e-3, [4096, 1000, 8192, 16384, 6000, 2, 3, 30000, 65536, 12288, 360]),
+    (1e-4, [4096, 1000, 2, 3, 360, 2048]),
+])
+def test_fp32_batch_mixed_lengths(delta, lengths):
+    sigs = [_signal(N, 100 + i).astype(np.float32) for i, N in enumerate(lengths)]
+    max_imfs = 7
+    print("case fp32 batch delta=%g" % delta, flush=True)
+    plan, packed, out = _run_batch(lengths, sigs, delta, max_imfs, torch.float32)
+    info = out.info()
+    n = out.n_imfs.cpu().numpy()
+    assert np.all(out.sig_status.cpu().numpy() == 0)
+    print("  oracle for %d signals" % len(lengths), flush=True)
+    refs = oracle_many([s.astype(np.float64) for s in sigs], delta, max_imfs)
+    for b, N in enumerate(lengths):
+        s64 = sigs[b].astype(np.float64)
+        ref = refs[b]
+        imfs = out.imfs_of(b).cpu().numpy().astype(np.float64)
+        rem = out.remainder_of(b).cpu().numpy().astype(np.float64)
+        _check(ref, s64, imfs, rem, info[b], int(n[b]), delta, False)
+
+
+def test_batch_is_independent_of_composition_and_deterministic():
+    lengths = [4096, 65536, 1000, 16384, 4096]
+    sigs = [_signal(N, 7 + i) for i, N in enumerate(lengths)]
+    plan, packed, out = _run_batch(lengths, sigs, 1e-3, 6, torch.float64)
+    out2 = plan.run(packed, 1e-3)
+    torch.cuda.synchronize()
+    assert torch.equal(out.imfs, out2.imfs) and torch.equal(out.remainders, out2.remainders)
+    info = out.info()
+    for b in (0, 1, 2):
+        x = torch.tensor(sigs[b], dtype=torch.float64, device="cuda")
+        res = fif.decompose(x, 1e-3, 6)
+        torch.cuda.synchronize()
+        k = res.n_imfs
+        assert k == int(out.n_imfs[b])
+        assert torch.equal(res.imfs, out.imfs_of(b)[:k])
+        assert torch.equal(res.remainder, out.remainder_of(b))
+        assert np.array_equal(res.info, info[b][:k])
+    # permuted batch gives the same bits per signal
+    perm = [2, 0, 4, 1, 3]
+    p2, _, o2 = _run_batch([lengths[i] for i in perm], [sigs[i] for i in perm], 1e-3, 6, torch.float64)
+    for nb, ob in enumerate(perm):
+        assert torch.equal(o2.imfs_of(nb), out.imfs_of(ob))
+
+
+def test_edge_cases():
+    N = 512
+    x = siggen.grid(N)
+    cases = {
+        "constant": np.full(N, 2.5),
+        "zero": np.zeros(N),
+        "ramp": x * x,
+        "nan": np.where(np.arange(N) == 17, np.nan, np.cos(2 * np.pi * 9 * x)),
+        "inf": np.where(np.arange(N) == 3, np.inf, np.cos(2 * np.pi * 9 * x)),
+        "tones": siggen.tones3(N=N, freqs=(3, 17, 60)),
+    }
+    names = list(cases)
+    plan, packed, out = _run_batch([N] * len(names), [cases[k] for k in names], 1e-3, 5, torch.float64)
+    st = out.sig_status.cpu().numpy()
+    n = out.n_imfs.cpu().numpy()
+    for b, k in enumerate(names):
+        s = cases[k]
+        rem = out.remainder_of(b).cpu().numpy()
+        imfs = out.imfs_of(b).cpu().numpy()
+        if k in ("nan", "inf"):
+            assert st[b] == fif._binding.FIF_ERR_NONFINITE and n[b] == 0
+            assert np.array_equal(rem, s, equal_nan=True) and np.all(imfs == 0)
+            continue
+        assert st[b] == 0
+        ref = dif.decompose(s, 1e-3, 5)
+        assert n[b] == ref.n_imfs, k
+        if ref.n_imfs == 0:
+            assert np.all(imfs == 0)
+            assert np.max(np.abs(rem - s)) <= 1e-15 * max(1.0, np.max(np.abs(s)))
+    xs = torch.tensor(cases["nan"], dtype=torch.float64, device="cuda")
+    with pytest.raises(fif.FifError):
+        fif.decompose(xs, 1e-3, 4)
+
+
+def test_cap_on_a_pure_tone():
+    N = 256
+    s = np.cos(2 * np.pi * 8 * np.arange(N) / N)
+    ref = dif.decompose(s, 1e-6, 1, max_inner=50)
+    x = torch.tensor(s, dtype=torch.float64, device="cuda")
+    res = fif.decompose(x, 1e-6, 1, fif.Options(max_inner=50))
+    assert int(res.info["m"][0]) == 50 == ref.m[0]
+    assert res.info["flags"][0] & fif.IMF_CAP
+    assert abs(res.info["sd"][0] - ref.sd[0]) < 1e-13
+
+
+@pytest.mark.parametrize("N", [4096, 65536])
+def test_mask_rule_paper_constant(N):
+    s = _signal(N, 3)
+    ref = dif.decompose(s, 1e-3, 5, mask_rule=1, nu=1.6)
+    x = torch.tensor(s, dtype=torch.float64, device="cuda")
+    res = fif.decompose(x, 1e-3, 5, fif.Options(mask_rule=1, nu=1.6))
+    imfs = np.zeros((5, N))
+    imfs[:res.n_imfs] = res.imfs.cpu().numpy()
+    _check(ref, s, imfs, res.remainder.cpu().numpy(), res.info, res.n_imfs, 1e-3, True)
+
+
+def test_chirp_batch_full_size_sampled():
+    """1024 signals of N = 65536 (2-6 AM chirps, 30 dB noise), FP32,
+    delta 1e-3, 12 IMFs: the benchmark's configuration.  Three signals are
+    checked against the oracle; every signal reconstructs."""
+    B, N, J = 1024, 65536, 12
+    print("case chirp batch B=%d N=%d" % (B, N), flush=True)
+    sigs = [siggen.chirps(i).astype(np.float32) for i in range(B)]
+    plan, packed, out = _run_batch([N] * B, sigs, 1e-3, J, torch.float32)
+    assert int(out.sig_status.abs().sum()) == 0
+    n = out.n_imfs.cpu().numpy()
+    assert n.min() >= 1
+    # reconstruction of every signal (sum of IMF rows + remainder = signal)
+    im = out.imfs.view(B, J, N).double()
+    recon = im.sum(1) + out.remainders.view(B, N).double()
+    err = (recon - packed.view(B, N).double()).norm(dim=1) / packed.view(B, N).double().norm(dim=1)
+    assert float(err.max()) < 1e-6
+    info = out.info()
+    picks = (0, 1, 511, 1023)
+    print("  oracle for signals %s" % (picks,), flush=True)
+    refs = oracle_many([sigs[b].astype(np.float64) for b in picks], 1e-3, J)
+    for b, ref in zip(picks, refs):
+        s64 = sigs[b].astype(np.float64)
+        _check(ref, s64, out.imfs_of(b).cpu().numpy().astype(np.float64),
+               out.remainder_of(b).cpu().numpy().astype(np.float64), info[b], int(n[b]), 1e-3, False)
