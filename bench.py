@@ -184,6 +184,13 @@ def main():
         st = out.sig_status.cpu().numpy()
         assert np.all(st == 0), "non-finite synthetic input"
         log("IMFs per signal: min %d mean %.2f max %d" % (n_imfs.min(), n_imfs.mean(), n_imfs.max()))
+        inf = out.info()
+        mask = np.arange(J)[None, :] < n_imfs[:, None]
+        ev = inf["evals"][mask]
+        log("search per IMF: FP32 passes mean %.2f max %d, FP64 evaluations mean %.3f max %d, refined %.2f%%, "
+            "m median %d max %d" % ((ev & 0xffff).mean(), (ev & 0xffff).max(), (ev >> 16).mean(), (ev >> 16).max(),
+                                    100.0 * np.mean(inf["flags"][mask] & 2 > 0), np.median(inf["m"][mask]),
+                                    inf["m"][mask].max()))
         rows = []
         for kind, (launches, ms) in prof.items():
             alg = algorithmic_bytes(kind, lengths, n_imfs, J, esize) * args.steps

@@ -27,8 +27,8 @@
  *     stops when max|r - mean(r)| <= floor_tau * max|s| (rounding floor) and
  *     after max_imfs IMFs; m is capped at max_inner (flag FIF_IMF_CAP).
  *   - Signal lengths: N >= 2 whose prime factors are all <= 7; lengths above
- *     8192 must split as N1*N2 with N1, N2 <= 8192.  Otherwise
- *     FIF_ERR_UNSUPPORTED_LENGTH and nothing is launched.
+ *     8192 must split as N1*N2 with N1, N2 <= 4096 (so N <= 2^24).
+ *     Otherwise FIF_ERR_UNSUPPORTED_LENGTH and nothing is launched.
  *   - Buffers: every array argument except `lengths` of fif_plan_create is a
  *     caller-owned DEVICE pointer (HBM of the current HIP device).  The
  *     library never frees or retains them.  Packed batches put signal b at
@@ -99,7 +99,8 @@ typedef struct {
     double sd;           /* SD_m (FP64, Parseval) */
     double sd_prev;      /* SD_{m-1}; +inf when m == 1 */
     uint32_t flags;      /* FIF_IMF_* */
-    int32_t reserved;
+    uint32_t evals;      /* low 16 bits: FP32 passes over the spectrum in the
+                            search for m; high 16 bits: FP64 evaluations */
 } fif_imf_info;
 
 typedef struct fif_plan fif_plan;

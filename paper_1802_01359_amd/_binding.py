@@ -54,7 +54,7 @@ class KernelTime(ctypes.Structure):
 
 
 IMF_INFO_DTYPE = np.dtype([("k", "<i8"), ("L", "<i8"), ("m", "<i8"), ("sd", "<f8"), ("sd_prev", "<f8"),
-                           ("flags", "<u4"), ("reserved", "<i4")])
+                           ("flags", "<u4"), ("evals", "<u4")])
 assert IMF_INFO_DTYPE.itemsize == 48
 
 

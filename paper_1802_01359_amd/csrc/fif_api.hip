@@ -106,7 +106,8 @@ struct fif_plan {
     double* d_dtab = nullptr;
     double2* d_ctab = nullptr;
     // workspace layout (byte offsets)
-    size_t ws_state = 0, ws_spec0 = 0, ws_spec1 = 0, ws_inter = 0, ws_parts = 0, ws_gscr = 0, ws_total = 0;
+    size_t ws_state = 0, ws_spec0 = 0, ws_spec1 = 0, ws_inter = 0, ws_parts = 0, ws_psum = 0, ws_gscr = 0,
+           ws_total = 0;
     // kernel timing (fif_plan_profile)
     struct Rec {
         int kind;
@@ -188,24 +189,25 @@ fif_status plan_length(int64_t N, LenPlan& lp)
         lp.TC = lp.TR = 1;
         return FIF_OK;
     }
-    // N = N1 * N2, both <= cap, max(N1, N2) smallest
+    // N = N1 * N2, both <= kTileCap (the four-step kernels stage at most
+    // kTileCap elements per workgroup), max(N1, N2) smallest
     int64_t best1 = -1;
-    for (int64_t n2 = 1; n2 <= kFftCap; ++n2) {
+    for (int64_t n2 = 1; n2 <= kTileCap; ++n2) {
         if (N % n2) continue;
         const int64_t n1 = N / n2;
-        if (n1 > kFftCap) continue;
+        if (n1 > kTileCap) continue;
         if (best1 < 0 || std::max(n1, n2) < std::max(best1, N / best1)) best1 = n1;
     }
     if (best1 < 0)
         return fail(FIF_ERR_UNSUPPORTED_LENGTH, "length %lld does not split into two factors <= %d",
-                    (long long)N, kFftCap);
+                    (long long)N, kTileCap);
     lp.two_pass = 1;
     lp.N1 = (int32_t)best1;
     lp.N2 = (int32_t)(N / best1);
     if (!make_subfft(lp.N2, lp.f1) || !make_subfft(lp.N1, lp.f2))
         return fail(FIF_ERR_UNSUPPORTED_LENGTH, "length %lld has a prime factor > 7", (long long)N);
-    lp.TC = (int32_t)largest_divisor_at_most(lp.N1, kFftCap / lp.N2);
-    lp.TR = (int32_t)largest_divisor_at_most(lp.N2, kFftCap / lp.N1);
+    lp.TC = (int32_t)largest_divisor_at_most(lp.N1, kTileCap / lp.N2);
+    lp.TR = (int32_t)largest_divisor_at_most(lp.N2, kTileCap / lp.N1);
     int64_t split = 1;
     while (split * split < N) split *= 2;
     lp.big_split = (int32_t)split;
@@ -374,6 +376,8 @@ fif_status fif_plan_create(fif_plan** out, const int64_t* lengths, int32_t B, in
     ws += sizeof(double2) * (size_t)inter;
     p->ws_parts = ws = align_up(ws, 256);
     ws += sizeof(RunState) * (size_t)parts;
+    p->ws_psum = ws = align_up(ws, 256);
+    ws += sizeof(double) * (size_t)parts;
     p->ws_gscr = ws = align_up(ws, 256);
     ws += sizeof(float) * (size_t)gscr;
     p->ws_total = align_up(ws, 256);
@@ -524,6 +528,7 @@ Bound bind(const fif_plan* p, void* ws, double delta, fif_imf_info* info)
     S.list = nullptr;
     S.st = b.state;
     S.parts = A.parts;
+    S.psum = (const double*)(w + p->ws_psum);
     S.dtab = p->d_dtab;
     S.spec0 = A.spec0;
     S.spec1 = A.spec1;
@@ -549,7 +554,8 @@ void launch_init(const fif_plan* p, Bound& b, const T* x, hipStream_t s)
     }
     if (!p->w_init.empty()) {
         Timed tm(p, "init_stats", s);
-        k_init_stats<T><<<(unsigned)p->w_init.size(), kFftThreads, 0, s>>>(p->d_sigs, p->d_init, x, b.sa.parts);
+        k_init_stats<T><<<(unsigned)p->w_init.size(), kFftThreads, 0, s>>>(p->d_sigs, p->d_init, x, b.sa.parts,
+                                                                           (double*)b.sc.psum, b.state);
     }
     StepArgs A = b.sa;
     if (!p->w_single.empty()) {

@@ -141,30 +141,59 @@ template <bool INV> struct Dft<3, INV> : DftOdd<3, INV> {};
 template <bool INV> struct Dft<5, INV> : DftOdd<5, INV> {};
 template <bool INV> struct Dft<7, INV> : DftOdd<7, INV> {};
 
-template <int R, bool INV>
+// x / d and x % d for 0 <= x < 2^24, 1 <= d < 2^16: the FP32 quotient is
+// off by at most one, fixed with one correction.
+struct FastDiv {
+    float r;
+    int d;
+};
+__device__ __forceinline__ FastDiv fastdiv(int d) { return {1.0f / (float)d, d}; }
+__device__ __forceinline__ int fdivmod(int x, FastDiv f, int& rem)
+{
+    int q = (int)((float)x * f.r);
+    int r = x - q * f.d;
+    if (r < 0) {
+        q -= 1;
+        r += f.d;
+    } else if (r >= f.d) {
+        q += 1;
+        r -= f.d;
+    }
+    rem = r;
+    return q;
+}
+
+// One Stockham pass over `batch` interleaved sequences, CAP >= n * batch.
+template <int R, bool INV, int CAP>
 __device__ __forceinline__ void fft_pass(double2* __restrict__ buf, int n, int batch, int ns,
                                          const double2* __restrict__ tw)
 {
-    constexpr int Q = (kFftCap / R + kFftThreads - 1) / kFftThreads;
+    constexpr int Q = (CAP / R + kFftThreads - 1) / kFftThreads;
     const int nb = n / R;
     const int items = nb * batch;
+    const FastDiv fb = fastdiv(batch), fn = fastdiv(ns);
     double2 v[Q][R];
+    int jq[Q], cq[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const int it = threadIdx.x + q * kFftThreads;
+        int c = 0, j = 0;
         if (it < items) {
-            const int c = it % batch, j = it / batch;
+            j = fdivmod(it, fb, c);
 #pragma unroll
             for (int r = 0; r < R; ++r) v[q][r] = buf[(j + r * nb) * batch + c];
         }
+        jq[q] = j;
+        cq[q] = c;
     }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const int it = threadIdx.x + q * kFftThreads;
         if (it < items) {
-            const int c = it % batch, j = it / batch;
-            const int k = j % ns;
+            const int c = cq[q], j = jq[q];
+            int k;
+            const int jd = fdivmod(j, fn, k);
             if (ns > 1) {
                 double2 w = tw[k];
                 if (INV) w.y = -w.y;
@@ -176,7 +205,7 @@ __device__ __forceinline__ void fft_pass(double2* __restrict__ buf, int n, int b
                 }
             }
             Dft<R, INV>::run(v[q]);
-            const int base = (j - k) * R + k;
+            const int base = jd * ns * R + k;
 #pragma unroll
             for (int r = 0; r < R; ++r) buf[(base + r * ns) * batch + c] = v[q][r];
         }
@@ -184,23 +213,23 @@ __device__ __forceinline__ void fft_pass(double2* __restrict__ buf, int n, int b
     __syncthreads();
 }
 
-// Transform `batch` interleaved sequences of length f.n in place.
-// Caller must __syncthreads() after filling buf.
-template <bool INV>
+// Transform `batch` interleaved sequences of length f.n in place
+// (f.n * batch <= CAP).  Caller must __syncthreads() after filling buf.
+template <bool INV, int CAP>
 __device__ __forceinline__ void lds_fft(double2* __restrict__ buf, const SubFft& f, int batch,
-                        const double2* __restrict__ twbase)
+                                        const double2* __restrict__ twbase)
 {
     const double2* tw = twbase + f.tw_off;
     int ns = 1;
     for (int p = 0; p < f.nrad; ++p) {
         const int R = f.rad[p];
         switch (R) {
-        case 2: fft_pass<2, INV>(buf, f.n, batch, ns, tw); break;
-        case 3: fft_pass<3, INV>(buf, f.n, batch, ns, tw); break;
-        case 4: fft_pass<4, INV>(buf, f.n, batch, ns, tw); break;
-        case 5: fft_pass<5, INV>(buf, f.n, batch, ns, tw); break;
-        case 7: fft_pass<7, INV>(buf, f.n, batch, ns, tw); break;
-        default: fft_pass<8, INV>(buf, f.n, batch, ns, tw); break;
+        case 2: fft_pass<2, INV, CAP>(buf, f.n, batch, ns, tw); break;
+        case 3: fft_pass<3, INV, CAP>(buf, f.n, batch, ns, tw); break;
+        case 4: fft_pass<4, INV, CAP>(buf, f.n, batch, ns, tw); break;
+        case 5: fft_pass<5, INV, CAP>(buf, f.n, batch, ns, tw); break;
+        case 7: fft_pass<7, INV, CAP>(buf, f.n, batch, ns, tw); break;
+        default: fft_pass<8, INV, CAP>(buf, f.n, batch, ns, tw); break;
         }
         tw += ns;
         ns *= R;

@@ -1,10 +1,12 @@
 // gfx950 kernels of the batched FIF hot path.
 //
 // Per outer step t (Algorithm 2, one IMF):
-//   k_scan     combine the run summaries of the residual (extrema count,
-//              min/max, at t = 0 also the sum), apply the stop rules, fix L,
-//              then pick m: FP32 exponential + bisection search on the
-//              Parseval form of SD, confirmed by FP64 sums at m and m-1;
+//   k_scan     combine the run summaries of the residual (extrema count; the
+//              min/max come from order-independent atomics), apply the stop
+//              rules, fix L, then pick m: one FP32 pass over geometric
+//              candidates, safeguarded regula falsi on the Parseval form of
+//              SD in FP32, and an FP64 confirmation SD_m <= delta < SD_{m-1}
+//              (exact FP64 search around the estimate if it fails);
 //   k_single / k_pass1 + k_pass2
 //              the inverse transform of z = (g + i (1 - g)) R_hat with
 //              g = (1 - lambda)^m: real part = IMF (Theorem 5 / Section 4
@@ -28,9 +30,6 @@ __device__ __forceinline__ RunState run_empty()
 {
     RunState r;
     r.first = r.last = 0.0;
-    r.mn = INFINITY;
-    r.mx = -INFINITY;
-    r.sum = 0.0;
     r.cnt = 0;
     r.fs = r.ls = 0;
     r.empty = 1;
@@ -53,9 +52,6 @@ __device__ __forceinline__ void run_push(RunState& r, double v)
         }
         r.last = v;
     }
-    r.mn = fmin(r.mn, v);
-    r.mx = fmax(r.mx, v);
-    r.sum += v;
 }
 
 // a then b
@@ -77,9 +73,6 @@ __device__ __forceinline__ RunState run_combine(const RunState& a, const RunStat
     r.cnt = cnt;
     r.first = a.first;
     r.last = b.last;
-    r.mn = fmin(a.mn, b.mn);
-    r.mx = fmax(a.mx, b.mx);
-    r.sum = a.sum + b.sum;
     r.empty = 0;
     r.nonfinite = a.nonfinite | b.nonfinite;
     return r;
@@ -90,9 +83,6 @@ __device__ __forceinline__ RunState run_shfl_down(const RunState& r, int off)
     RunState o;
     o.first = __shfl_down(r.first, off);
     o.last = __shfl_down(r.last, off);
-    o.mn = __shfl_down(r.mn, off);
-    o.mx = __shfl_down(r.mx, off);
-    o.sum = __shfl_down(r.sum, off);
     o.cnt = __shfl_down(r.cnt, off);
     int packed = (int)(uint8_t)r.fs | ((int)(uint8_t)r.ls << 8) | ((int)r.empty << 16) |
                  ((int)r.nonfinite << 24);
@@ -126,80 +116,119 @@ __device__ __forceinline__ RunState block_run_reduce(RunState r, RunState* sh)
     return tot;
 }
 
-// ------------------------------------------------------------ reductions --
-
-template <typename T, int NT>
-__device__ __forceinline__ void block_sum2(T& a, T& b, T* sh)
+// order-preserving integer key of a double (for atomic min / max)
+__device__ __forceinline__ long long dkey(double v)
 {
-    constexpr int NW = NT / 64;
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        a += __shfl_xor(a, off);
-        b += __shfl_xor(b, off);
-    }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) {
-        sh[2 * wave] = a;
-        sh[2 * wave + 1] = b;
-    }
-    __syncthreads();
-    T sa = 0, sb = 0;
-#pragma unroll
-    for (int w = 0; w < NW; ++w) {
-        sa += sh[2 * w];
-        sb += sh[2 * w + 1];
-    }
-    __syncthreads();
-    a = sa;
-    b = sb;
+    const long long b = __double_as_longlong(v);
+    return b >= 0 ? b : (b ^ 0x7fffffffffffffffLL);
+}
+__device__ __forceinline__ double dval(long long k)
+{
+    return __longlong_as_double(k >= 0 ? k : (k ^ 0x7fffffffffffffffLL));
 }
 
-template <typename T, int NT>
-__device__ __forceinline__ void block_sum4(T* v, T* sh)
+// ------------------------------------------------------------ reductions --
+
+// Sum of NV values per thread over the block; every thread gets the totals
+// (same order everywhere: deterministic).  sh: NV * NT/64 elements.
+template <typename T, int NT, int NV>
+__device__ __forceinline__ void block_sum(T* v, T* sh)
 {
     constexpr int NW = NT / 64;
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) v[i] += __shfl_xor(v[i], off);
+        for (int i = 0; i < NV; ++i) v[i] += __shfl_xor(v[i], off);
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) sh[4 * wave + i] = v[i];
+        for (int i = 0; i < NV; ++i) sh[NV * wave + i] = v[i];
     }
     __syncthreads();
-    T s[4] = {0, 0, 0, 0};
 #pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        T s = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) s += sh[NV * w + i];
+        v[i] = s;
+    }
+    __syncthreads();
+}
+
+// min and max over the block, result in every thread
+template <int NT>
+__device__ __forceinline__ void block_minmax(double& mn, double& mx, double* sh)
+{
+    constexpr int NW = NT / 64;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        mn = fmin(mn, __shfl_xor(mn, off));
+        mx = fmax(mx, __shfl_xor(mx, off));
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        sh[2 * wave] = mn;
+        sh[2 * wave + 1] = mx;
+    }
+    __syncthreads();
     for (int w = 0; w < NW; ++w) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) s[i] += sh[4 * w + i];
+        mn = fmin(mn, sh[2 * w]);
+        mx = fmax(mx, sh[2 * w + 1]);
     }
     __syncthreads();
-#pragma unroll
-    for (int i = 0; i < 4; ++i) v[i] = s[i];
 }
 
 // ------------------------------------------------------ window spectrum --
 
+// (a * b) mod n for a*b < 2^53: the product and q*n are exact in FP64,
+// the rounded quotient is off by at most one.
+__device__ __forceinline__ int64_t mulmod53(int64_t a, int64_t b, int64_t n)
+{
+    const double p = (double)a * (double)b;
+    const double dn = (double)n;
+    const double q = floor(p / dn);
+    int64_t r = (int64_t)(p - q * dn);
+    if (r < 0) r += n;
+    if (r >= n) r -= n;
+    return r;
+}
+
 // lambda_j = [sin(pi L j / N) / (L sin(pi j / N))]^4, the DFT of the
-// circulant column of the triangle-squared window, with L*j reduced mod N in
-// integers and both sines read from sin(pi u/N), u <= N/2.
+// circulant column of the triangle-squared window, with L*j reduced mod N
+// exactly and both sines read from sin(pi u/N), u <= N/2.
 __device__ __forceinline__ double lambda_at(int64_t j, int64_t N, int64_t Lmod, double Ld,
                                             const double* __restrict__ sinT)
 {
     if (j == 0) return 1.0;
-    int64_t t = (Lmod * j) % N;
+    int64_t t = mulmod53(Lmod, j, N);
     if (t > N - t) t = N - t;
     const double q = sinT[t] / (Ld * sinT[j]);
     const double q2 = q * q;
     return q2 * q2;
 }
 
+// x^e by binary powering (e >= 0)
+__device__ __forceinline__ double ipow(double x, int64_t e)
+{
+    double r = 1.0;
+    while (e) {
+        if (e & 1) r *= x;
+        x *= x;
+        e >>= 1;
+    }
+    return r;
+}
+
+// Exponent above which (1 - lambda)^e is taken as exp(e log1p(-lambda)):
+// binary powering carries a relative error of about e ulps of 1 - lambda.
+constexpr int64_t kPowByMul = 1023;
+
 // (1 - lambda)^m
 __device__ __forceinline__ double gain_pow(double lam, int64_t m)
 {
     if (lam >= 1.0) return 0.0;
+    if (m <= kPowByMul) return ipow(1.0 - lam, m);
     return exp((double)m * log1p(-lam));
 }
 
@@ -211,7 +240,7 @@ __global__ void k_fill_sin(double* __restrict__ out, int64_t N, int64_t count)
     if (u < count) out[u] = sinpi((double)u / (double)N);
 }
 
-// exp(-2 pi i k / den) for k < count, written at out[k]
+// exp(-2 pi i k stride / den) for k < count, written at out[k]
 __global__ void k_fill_roots(double2* __restrict__ out, int64_t den, int64_t count, int64_t stride)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -233,15 +262,18 @@ __device__ __forceinline__ double2 big_twiddle(const LenPlan& lp, const double2*
 
 // ------------------------------------------------------- init statistics --
 
-// Run summary of one tile of the input signal (first outer step's count,
-// min/max, sum and non-finite check).
+// Run summary, sum, min and max of one tile of the input signal (first
+// outer step's count and rounding floor, non-finite check).
 template <typename InT>
 __global__ __launch_bounds__(kFftThreads) void k_init_stats(const SigDesc* __restrict__ sigs,
                                                              const Work* __restrict__ work,
                                                              const InT* __restrict__ x,
-                                                             RunState* __restrict__ parts)
+                                                             RunState* __restrict__ parts,
+                                                             double* __restrict__ psum,
+                                                             SigState* __restrict__ st)
 {
     __shared__ RunState sh[kFftThreads / 64];
+    __shared__ double shd[2 * (kFftThreads / 64)];
     const Work w = work[blockIdx.x];
     const SigDesc d = sigs[w.sig];
     const int64_t t0 = (int64_t)w.tile * kFftCap;
@@ -249,9 +281,24 @@ __global__ __launch_bounds__(kFftThreads) void k_init_stats(const SigDesc* __res
     const int chunk = (int)((len + kFftThreads - 1) / kFftThreads);
     const int64_t a = (int64_t)threadIdx.x * chunk, b = min(len, a + chunk);
     RunState r = run_empty();
-    for (int64_t i = a; i < b; ++i) run_push(r, (double)x[d.off + t0 + i]);
+    double s = 0.0, mn = INFINITY, mx = -INFINITY;
+    for (int64_t i = a; i < b; ++i) {
+        const double v = (double)x[d.off + t0 + i];
+        run_push(r, v);
+        s += v;
+        mn = fmin(mn, v);
+        mx = fmax(mx, v);
+    }
+    double sv[1] = {s};
+    block_sum<double, kFftThreads, 1>(sv, shd);
+    block_minmax<kFftThreads>(mn, mx, shd);
     r = block_run_reduce<kFftThreads>(r, sh);
-    if (threadIdx.x == 0) parts[d.part_off + w.tile] = r;
+    if (threadIdx.x == 0) {
+        parts[d.part_off + w.tile] = r;
+        psum[d.part_off + w.tile] = sv[0];
+        atomicMin(&st[w.sig].kmin, dkey(mn));
+        atomicMax(&st[w.sig].kmax, dkey(mx));
+    }
 }
 
 // ------------------------------------------------------ transform modes --
@@ -289,15 +336,16 @@ __device__ __forceinline__ double2 step_input(double2 v, bool mirror, double g, 
 // -------------------------------------------------- single LDS pass (N <= cap)
 
 // One workgroup per signal.  FORWARD: real input -> half spectrum (buffer 0)
-// and nothing else.  STEP: apply, inverse transform, IMF row t, run summary of
-// the residual, next spectrum.  REMAINDER: inverse transform of the final
-// spectrum, imaginary part only.
+// and nothing else.  STEP: apply, inverse transform, IMF row t, run summary,
+// min and max of the residual, next spectrum.  REMAINDER: inverse transform
+// of the final spectrum, imaginary part only.
 template <int MODE, typename InT, typename OutT>
 __global__ __launch_bounds__(kFftThreads) void k_single(StepArgs A, const InT* __restrict__ x,
                                                         OutT* __restrict__ imfs, OutT* __restrict__ rem)
 {
     extern __shared__ double2 lds[];
     __shared__ RunState sh[kFftThreads / 64];
+    __shared__ double shd[2 * (kFftThreads / 64)];
     const Work w = A.work[blockIdx.x];
     const SigDesc d = A.sigs[w.sig];
     const LenPlan& lp = A.lens[d.len_id];
@@ -308,7 +356,7 @@ __global__ __launch_bounds__(kFftThreads) void k_single(StepArgs A, const InT* _
     if (MODE == MODE_FORWARD) {
         for (int k = threadIdx.x; k < N; k += kFftThreads) lds[k] = make_double2((double)x[d.off + k], 0.0);
         __syncthreads();
-        lds_fft<false>(lds, lp.f1, 1, A.ctab);
+        lds_fft<false, kFftCap>(lds, lp.f1, 1, A.ctab);
         double2* out = A.spec0 + d.spec_off;
         for (int k = threadIdx.x; k <= nh; k += kFftThreads) out[k] = lds[k];
         return;
@@ -338,7 +386,7 @@ __global__ __launch_bounds__(kFftThreads) void k_single(StepArgs A, const InT* _
         if (MODE == MODE_STEP) Rout[j] = cscale(v, 1.0 - g);
     }
     __syncthreads();
-    lds_fft<true>(lds, lp.f1, 1, A.ctab);
+    lds_fft<true, kFftCap>(lds, lp.f1, 1, A.ctab);
     if (MODE == MODE_REMAINDER) {
         for (int k = threadIdx.x; k < N; k += kFftThreads) rem[d.off + k] = (OutT)lds[k].y;
         return;
@@ -348,9 +396,20 @@ __global__ __launch_bounds__(kFftThreads) void k_single(StepArgs A, const InT* _
     const int chunk = (N + kFftThreads - 1) / kFftThreads;
     const int a = threadIdx.x * chunk, b = min(N, a + chunk);
     RunState r = run_empty();
-    for (int i = a; i < b; ++i) run_push(r, lds[i].y);
+    double mn = INFINITY, mx = -INFINITY;
+    for (int i = a; i < b; ++i) {
+        const double y = lds[i].y;
+        run_push(r, y);
+        mn = fmin(mn, y);
+        mx = fmax(mx, y);
+    }
+    block_minmax<kFftThreads>(mn, mx, shd);
     r = block_run_reduce<kFftThreads>(r, sh);
-    if (threadIdx.x == 0) A.parts[d.part_off] = r;
+    if (threadIdx.x == 0) {
+        A.parts[d.part_off] = r;
+        S->kmin = dkey(mn);
+        S->kmax = dkey(mx);
+    }
 }
 
 // ----------------------------------------------- four-step pass 1 (columns)
@@ -372,9 +431,11 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
     if (MODE == MODE_STEP && !S->active) return;
     if (MODE == MODE_REMAINDER && S->status != 0) return;
     const int total = TC * N2;
+    const FastDiv ftc = fastdiv(TC);
     if (MODE == MODE_FORWARD) {
         for (int f = threadIdx.x; f < total; f += kFftThreads) {
-            const int cl = f % TC, r = f / TC;
+            int cl;
+            const int r = fdivmod(f, ftc, cl);
             lds[f] = make_double2((double)x[d.off + c0 + cl + (int64_t)N1 * r], 0.0);
         }
     } else {
@@ -387,7 +448,8 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
         const double* sinT = A.dtab + lp.sin_off;
         const int64_t nh = N / 2;
         for (int f = threadIdx.x; f < total; f += kFftThreads) {
-            const int cl = f % TC, r = f / TC;
+            int cl;
+            const int r = fdivmod(f, ftc, cl);
             const int64_t k = c0 + cl + (int64_t)N1 * r;
             const bool mirror = k > nh;
             const int64_t j = mirror ? N - k : k;
@@ -400,12 +462,13 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
     }
     __syncthreads();
     if (MODE == MODE_FORWARD)
-        lds_fft<false>(lds, lp.f1, TC, A.ctab);
+        lds_fft<false, kTileCap>(lds, lp.f1, TC, A.ctab);
     else
-        lds_fft<true>(lds, lp.f1, TC, A.ctab);
+        lds_fft<true, kTileCap>(lds, lp.f1, TC, A.ctab);
     double2* Y = A.inter + d.inter_off;
     for (int f = threadIdx.x; f < total; f += kFftThreads) {
-        const int cl = f % TC, rp = f / TC;
+        int cl;
+        const int rp = fdivmod(f, ftc, cl);
         const int c = c0 + cl;
         const int64_t a = (int64_t)rp * c;
         double2 v = lds[f];
@@ -421,13 +484,15 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
 // -------------------------------------------------- four-step pass 2 (rows)
 
 // Work tile = TR consecutive rows r' of Y.  Transforms each row over c
-// (length N1); output element N2 * c' + r'.  STEP: IMF and one run summary
-// per c' (TR consecutive samples); FORWARD: half spectrum; REMAINDER: y.
+// (length N1); output element N2 * c' + r'.  STEP: IMF, one run summary per
+// c' (TR consecutive samples) and the tile's min/max; FORWARD: half
+// spectrum; REMAINDER: y.
 template <int MODE, typename InT, typename OutT>
 __global__ __launch_bounds__(kFftThreads) void k_pass2(StepArgs A, const InT* __restrict__ x,
                                                        OutT* __restrict__ imfs, OutT* __restrict__ rem)
 {
     extern __shared__ double2 lds[];
+    __shared__ double shd[2 * (kFftThreads / 64)];
     const Work w = A.work[blockIdx.x];
     const SigDesc d = A.sigs[w.sig];
     const LenPlan& lp = A.lens[d.len_id];
@@ -436,17 +501,20 @@ __global__ __launch_bounds__(kFftThreads) void k_pass2(StepArgs A, const InT* __
     const int r0 = w.tile * TR;
     SigState* S = A.st + w.sig;
     const int total = TR * N1;
+    const FastDiv ftr = fastdiv(TR), fn1 = fastdiv(N1);
     if (MODE == MODE_STEP && !S->active) {
         OutT* row = imfs + (int64_t)A.max_imfs * d.off + (int64_t)A.t * N;
         for (int f = threadIdx.x; f < total; f += kFftThreads) {
-            const int cp = f / TR, rl = f % TR;
+            int rl;
+            const int cp = fdivmod(f, ftr, rl);
             row[(int64_t)N2 * cp + r0 + rl] = (OutT)0;
         }
         return;
     }
     if (MODE == MODE_REMAINDER && S->status != 0) {
         for (int f = threadIdx.x; f < total; f += kFftThreads) {
-            const int cp = f / TR, rl = f % TR;
+            int rl;
+            const int cp = fdivmod(f, ftr, rl);
             const int64_t n = (int64_t)N2 * cp + r0 + rl;
             rem[d.off + n] = (OutT)x[d.off + n];
         }
@@ -454,19 +522,21 @@ __global__ __launch_bounds__(kFftThreads) void k_pass2(StepArgs A, const InT* __
     }
     const double2* Y = A.inter + d.inter_off;
     for (int f = threadIdx.x; f < total; f += kFftThreads) {
-        const int rl = f / N1, c = f % N1;
+        int c;
+        const int rl = fdivmod(f, fn1, c);
         lds[c * TR + rl] = Y[(int64_t)(r0 + rl) * N1 + c];
     }
     __syncthreads();
     if (MODE == MODE_FORWARD)
-        lds_fft<false>(lds, lp.f2, TR, A.ctab);
+        lds_fft<false, kTileCap>(lds, lp.f2, TR, A.ctab);
     else
-        lds_fft<true>(lds, lp.f2, TR, A.ctab);
+        lds_fft<true, kTileCap>(lds, lp.f2, TR, A.ctab);
     if (MODE == MODE_FORWARD) {
         double2* out = A.spec0 + d.spec_off;
         const int64_t nh = N / 2;
         for (int f = threadIdx.x; f < total; f += kFftThreads) {
-            const int cp = f / TR, rl = f % TR;
+            int rl;
+            const int cp = fdivmod(f, ftr, rl);
             const int64_t n = (int64_t)N2 * cp + r0 + rl;
             if (n <= nh) out[n] = lds[f];
         }
@@ -474,21 +544,34 @@ __global__ __launch_bounds__(kFftThreads) void k_pass2(StepArgs A, const InT* __
     }
     if (MODE == MODE_REMAINDER) {
         for (int f = threadIdx.x; f < total; f += kFftThreads) {
-            const int cp = f / TR, rl = f % TR;
+            int rl;
+            const int cp = fdivmod(f, ftr, rl);
             rem[d.off + (int64_t)N2 * cp + r0 + rl] = (OutT)lds[f].y;
         }
         return;
     }
     OutT* row = imfs + (int64_t)A.max_imfs * d.off + (int64_t)A.t * N;
     for (int f = threadIdx.x; f < total; f += kFftThreads) {
-        const int cp = f / TR, rl = f % TR;
+        int rl;
+        const int cp = fdivmod(f, ftr, rl);
         row[(int64_t)N2 * cp + r0 + rl] = (OutT)lds[f].x;
     }
     const int runs_per_row = N2 / TR;
+    double mn = INFINITY, mx = -INFINITY;
     for (int cp = threadIdx.x; cp < N1; cp += kFftThreads) {
         RunState r = run_empty();
-        for (int rl = 0; rl < TR; ++rl) run_push(r, lds[cp * TR + rl].y);
+        for (int rl = 0; rl < TR; ++rl) {
+            const double y = lds[cp * TR + rl].y;
+            run_push(r, y);
+            mn = fmin(mn, y);
+            mx = fmax(mx, y);
+        }
         A.parts[d.part_off + cp * runs_per_row + w.tile] = r;
+    }
+    block_minmax<kFftThreads>(mn, mx, shd);
+    if (threadIdx.x == 0) {
+        atomicMin(&S->kmin, dkey(mn));
+        atomicMax(&S->kmax, dkey(mx));
     }
 }
 
@@ -500,6 +583,7 @@ struct ScanArgs {
     const int32_t* list;      // signal handled by each workgroup
     SigState* st;
     const RunState* parts;
+    const double* psum;       // per-tile sums of the input (first step)
     const double* dtab;
     const double2* spec0;
     const double2* spec1;
@@ -522,24 +606,23 @@ __device__ __forceinline__ int64_t mask_length(int64_t N, int64_t k, int rule, d
     return L < 1 ? 1 : L;
 }
 
-// Per-thread bins j = 1 + tid + i*T, i < BPT (fast path: tau and b in
-// registers, a in LDS at [i*T + tid]) -- or all bins via global scratch when
-// BPT == 0.
-template <int BPT>
-struct ScanBins {
-    float tau[BPT > 0 ? BPT : 1], b[BPT > 0 ? BPT : 1];
-};
+// Probes of the bracketing phase: m = 1, 2, 4, 16, ..., 4^10.
+constexpr int kGeo = 12;
+__device__ __forceinline__ int64_t geo_m(int q) { return q == 0 ? 1 : q == 1 ? 2 : ((int64_t)1 << (2 * (q - 1))); }
 
-// One workgroup per signal.
+// One workgroup per signal.  BPT > 0: thread-owned bins j = 1 + tid + i*T
+// (i < BPT) keep log2(mu) and the power in registers, power*lambda^2 in LDS;
+// BPT == 0: the same three FP32 values per bin live in global scratch.
 template <int BPT>
 __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
 {
     constexpr int T = kScanThreads;
+    constexpr int NR = BPT > 0 ? BPT : 1;
     __shared__ RunState shr[T / 64];
     __shared__ double shd[4 * (T / 64)];
-    __shared__ float shf[2 * (T / 64)];
-    __shared__ int64_t sh_i[4];
-    __shared__ double sh_pscale;
+    __shared__ float shf[2 * kGeo * (T / 64)];
+    __shared__ int64_t sh_i[2];
+    __shared__ double sh_d[1];
 
     const int s = A.list[blockIdx.x];
     const SigDesc d = A.sigs[s];
@@ -559,21 +642,30 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
         for (int i = a; i < b; ++i) r = run_combine(r, P[i]);
         r = block_run_reduce<T>(r, shr);
         if (tid == 0) {
+            const double mn = dval(S->kmin), mx = dval(S->kmax);
+            S->kmin = dkey(INFINITY);
+            S->kmax = dkey(-INFINITY);
             int stop = -1;
             if (A.t == 0) {
-                if (r.nonfinite) {
+                double sum = 0.0;
+                for (int i = 0; i < d.n_init_parts; ++i) sum += A.psum[d.part_off + i];
+                if (r.nonfinite || !isfinite(sum)) {
                     S->status = FIF_ERR_NONFINITE;
                     stop = FIF_STOP_FAILED;
                 } else {
-                    S->mean = r.sum / (double)N;
-                    S->maxabs = fmax(fabs(r.mn), fabs(r.mx));
-                    // power-of-two scale keeping the FP32 powers below 1
-                    const double top = (double)N * S->maxabs;
-                    S->pscale = top > 0.0 ? ldexp(1.0, -2 * (ilogb(top) + 1)) : 1.0;
+                    S->mean = sum / (double)N;
+                    S->maxabs = fmax(fabs(mn), fabs(mx));
                 }
             }
+            // power-of-two scale of this residual's power spectrum: |R_j| <=
+            // N max|r|, so the scaled FP32 powers stay below 2 and late, small
+            // residuals do not underflow
+            {
+                const double top = (double)N * fmax(fabs(mn), fabs(mx));
+                S->pscale = (top > 0.0 && isfinite(top)) ? ldexp(1.0, -2 * (ilogb(top) + 1)) : 1.0;
+            }
             if (stop < 0) {
-                const double dev = fmax(r.mx - S->mean, S->mean - r.mn);
+                const double dev = fmax(mx - S->mean, S->mean - mn);
                 if (dev <= A.floor_tau * S->maxabs)
                     stop = FIF_STOP_FLOOR;
                 else if (r.cnt < 2)
@@ -589,7 +681,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
                 S->k = r.cnt;
                 sh_i[0] = mask_length(N, r.cnt, A.mask_rule, A.nu);
             }
-            sh_pscale = S->pscale;
+            sh_d[0] = S->pscale;
         }
         __syncthreads();
     }
@@ -601,41 +693,41 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
     const double Ld = (double)L;
     const double* sinT = A.dtab + lp.sin_off;
     const double2* R = ((A.t & 1) ? A.spec1 : A.spec0) + d.spec_off;
-    const double pscale = sh_pscale;
+    const double pscale = sh_d[0];
     const double delta = A.delta;
     const float d2f = (float)(delta * delta);
+    const float lnd2 = logf(d2f);
     const int64_t cap = A.max_inner;
+    uint32_t n32 = 0, n64 = 0;
 
-    // ---- first sweep: FP32 copies of the weighted power, power*lambda^2,
-    //      log2 of mu = (1 - lambda)^2 (DC kept aside: lambda_0 = 1) ----
-    ScanBins<BPT> bins;
+    // ---- first sweep: FP32 copies of the weighted power b, power*lambda^2
+    //      a, and tau = log2 mu, mu = (1 - lambda)^2 (DC kept aside since
+    //      lambda_0 = 1 contributes to m = 1 only) ----
+    float tau_r[NR], b_r[NR];
     extern __shared__ float lds_a[];
     float* gs = (BPT == 0) ? (A.gscr + A.gscr_off[s]) : nullptr;
-    const int64_t nb = nh;  // bins 1..nh
     auto weight = [&](int64_t j) -> double { return (2 * j == N) ? 1.0 : 2.0; };
     auto sweep_bin = [&](int64_t j, float& tau, float& av, float& bv) {
         const double2 v = R[j];
         const double P = weight(j) * (v.x * v.x + v.y * v.y) * pscale;
         const double lam = lambda_at(j, N, Lmod, Ld, sinT);
+        const float lf = (float)lam;
         bv = (float)P;
         av = (float)(P * lam * lam);
-        tau = (float)(2.0 * log1p(-lam) * 1.4426950408889634);
+        tau = 2.8853900817779268f * log1pf(-lf);  // 2 log2(1 - lambda)
     };
     if (BPT > 0) {
 #pragma unroll
-        for (int i = 0; i < (BPT > 0 ? BPT : 1); ++i) {
+        for (int i = 0; i < NR; ++i) {
             const int64_t j = 1 + tid + (int64_t)i * T;
             float av = 0.f;
-            if (j <= nb) {
-                sweep_bin(j, bins.tau[i], av, bins.b[i]);
-            } else {
-                bins.tau[i] = 0.f;
-                bins.b[i] = 0.f;
-            }
+            tau_r[i] = 0.f;
+            b_r[i] = 0.f;
+            if (j <= nh) sweep_bin(j, tau_r[i], av, b_r[i]);
             lds_a[i * T + tid] = av;
         }
     } else {
-        for (int64_t j = 1 + tid; j <= nb; j += T) {
+        for (int64_t j = 1 + tid; j <= nh; j += T) {
             float tau, av, bv;
             sweep_bin(j, tau, av, bv);
             gs[3 * (j - 1)] = tau;
@@ -646,64 +738,135 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
     const double P0 = (R[0].x * R[0].x + R[0].y * R[0].y) * pscale;
     __syncthreads();
 
-    // SD_m <= delta in FP32: A(m) = sum a x, B(m) = sum b x, x = mu^(m-1)
-    auto ok32 = [&](int64_t m) -> bool {
-        float sa = 0.f, sb = 0.f;
-        const float c = (float)(m - 1);
+    // per-bin FP32 accumulation of a*x and b*x, x = mu^e = 2^(e tau)
+    auto acc_bin = [&](float tau, float av, float bv, float e, float& sa, float& sb) {
+        const float xx = __builtin_amdgcn_exp2f(e * tau);
+        sa += av * xx;
+        sb += bv * xx;
+    };
+
+    // f at an arbitrary m (one FP32 pass); m = 1 needs no power (and must not
+    // form 0 * tau with tau = -inf for bins whose FP32 lambda rounds to 1)
+    auto f32 = [&](int64_t m) -> float {
+        float v[2] = {0.f, 0.f};
+        const float e = (float)(m - 1);
         if (m == 1) {
             if (BPT > 0) {
 #pragma unroll
-                for (int i = 0; i < (BPT > 0 ? BPT : 1); ++i) {
-                    sa += lds_a[i * T + tid];
-                    sb += bins.b[i];
+                for (int i = 0; i < NR; ++i) {
+                    v[0] += lds_a[i * T + tid];
+                    v[1] += b_r[i];
                 }
             } else {
-                for (int64_t j = 1 + tid; j <= nb; j += T) {
-                    sa += gs[3 * (j - 1) + 1];
-                    sb += gs[3 * (j - 1) + 2];
+                for (int64_t j = 1 + tid; j <= nh; j += T) {
+                    v[0] += gs[3 * (j - 1) + 1];
+                    v[1] += gs[3 * (j - 1) + 2];
                 }
             }
-            if (tid == 0) {
-                sa += (float)P0;
-                sb += (float)P0;
-            }
-        } else {
-            if (BPT > 0) {
+        } else if (BPT > 0) {
 #pragma unroll
-                for (int i = 0; i < (BPT > 0 ? BPT : 1); ++i) {
-                    const float xx = exp2f(c * bins.tau[i]);
-                    sa += lds_a[i * T + tid] * xx;
-                    sb += bins.b[i] * xx;
-                }
-            } else {
-                for (int64_t j = 1 + tid; j <= nb; j += T) {
-                    const float xx = exp2f(c * gs[3 * (j - 1)]);
-                    sa += gs[3 * (j - 1) + 1] * xx;
-                    sb += gs[3 * (j - 1) + 2] * xx;
-                }
-            }
+            for (int i = 0; i < NR; ++i) acc_bin(tau_r[i], lds_a[i * T + tid], b_r[i], e, v[0], v[1]);
+        } else {
+            for (int64_t j = 1 + tid; j <= nh; j += T)
+                acc_bin(gs[3 * (j - 1)], gs[3 * (j - 1) + 1], gs[3 * (j - 1) + 2], e, v[0], v[1]);
         }
-        block_sum2<float, T>(sa, sb, shf);
-        return sb == 0.f || sa <= d2f * sb;
+        if (m == 1 && tid == 0) {
+            v[0] += (float)P0;
+            v[1] += (float)P0;
+        }
+        block_sum<float, T, 2>(v, shf);
+        n32 += 1;
+        return v[1] > 0.f ? (logf(v[0] / v[1]) - lnd2) : -INFINITY;
     };
 
-    // FP64 SD at exponents e and e+1 of mu (m = e+1 and e+2)
+    // ---- bracket by probing m = 1, 2, 4, 16, 64, ... (one FP32 pass each,
+    //      stopping at the first that satisfies the test), then safeguarded
+    //      regula falsi: smallest m <= cap with f(m) <= 0 (f is
+    //      non-increasing in m)
+    int64_t mt;
+    {
+        int64_t lo = 0, hi = -1;
+        float flo = INFINITY, fhi = 0.f;
+        for (int q = 0; q < kGeo; ++q) {
+            const int64_t mq = geo_m(q);
+            if (mq >= cap) break;
+            const float fq = f32(mq);
+            if (fq <= 0.f) {
+                hi = mq;
+                fhi = fq;
+                break;
+            }
+            lo = mq;
+            flo = fq;
+        }
+        if (hi < 0) {
+            // no probe below the cap satisfies the test
+            const float fc = f32(cap);
+            if (fc <= 0.f) {
+                hi = cap;
+                fhi = fc;
+            } else {
+                lo = cap;
+            }
+        }
+        if (hi < 0) {
+            mt = cap;
+        } else {
+            int side = 0;  // Illinois: endpoint kept twice in a row gets its f halved
+            int64_t last_width = hi - lo;
+            bool bisect = false;
+            while (hi - lo > 1) {
+                int64_t c;
+                if (bisect || lo == 0 || !isfinite(flo)) {
+                    c = lo + (hi - lo) / 2;
+                } else {
+                    const double fr = (double)flo / ((double)flo - (double)fhi);
+                    c = lo + (int64_t)llrint(fr * (double)(hi - lo));
+                }
+                c = max(lo + 1, min(hi - 1, c));
+                const float fc = f32(c);
+                if (fc <= 0.f) {
+                    hi = c;
+                    fhi = fc;
+                    if (side == 1) flo *= 0.5f;
+                    side = 1;
+                } else {
+                    lo = c;
+                    flo = fc;
+                    if (side == -1) fhi *= 0.5f;
+                    side = -1;
+                }
+                // force a bisection step when the bracket shrank less than half
+                const int64_t wdt = hi - lo;
+                bisect = (2 * wdt > last_width);
+                last_width = wdt;
+            }
+            mt = hi;
+        }
+    }
+
+    // ---- FP64 SD at m and m-1 (Parseval, FP64 lambda, powers and sums)
     auto sd64 = [&](int64_t m, double& sd_m, double& sd_mm1) {
-        // sums at m-1 (index 0,1) and m (index 2,3); e = m - 2 may be -1
         double v[4] = {0.0, 0.0, 0.0, 0.0};
-        const int64_t e = m - 2;
-        for (int64_t j = 1 + tid; j <= nb; j += T) {
+        const int64_t e = m - 2;  // exponent of mu at m-1; may be -1
+        for (int64_t j = 1 + tid; j <= nh; j += T) {
             const double2 z = R[j];
             const double P = weight(j) * (z.x * z.x + z.y * z.y) * pscale;
             const double lam = lambda_at(j, N, Lmod, Ld, sinT);
             const double l2 = lam * lam;
-            const double lg = 2.0 * log1p(-lam);  // log mu
-            const double xm = (lam >= 1.0) ? 0.0 : exp((double)(m - 1) * lg);
-            if (e >= 0) {
-                const double xe = (lam >= 1.0) ? (e == 0 ? 1.0 : 0.0) : exp((double)e * lg);
-                v[0] += P * l2 * xe;
-                v[1] += P * xe;
-            }
+            const double om = 1.0 - lam;
+            double xe;  // mu^e
+            if (e < 0)
+                xe = 0.0;
+            else if (lam >= 1.0)
+                xe = (e == 0) ? 1.0 : 0.0;
+            else if (e <= kPowByMul)
+                xe = ipow(om * om, e);
+            else
+                xe = exp((double)e * 2.0 * log1p(-lam));
+            const double xm = (e < 0) ? 1.0 : xe * om * om;  // mu^(m-1)
+            v[0] += P * l2 * xe;
+            v[1] += P * xe;
             v[2] += P * l2 * xm;
             v[3] += P * xm;
         }
@@ -717,41 +880,11 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
                 v[1] += P0;
             }
         }
-        block_sum4<double, T>(v, shd);
+        block_sum<double, T, 4>(v, shd);
+        n64 += 1;
         sd_m = v[3] > 0.0 ? sqrt(v[2] / v[3]) : 0.0;
         sd_mm1 = (m == 1) ? INFINITY : (v[1] > 0.0 ? sqrt(v[0] / v[1]) : 0.0);
     };
-
-    // ---- FP32 exponential search + bisection for the smallest m with
-    //      SD <= delta (SD is non-increasing in m); mt = cap if none is found
-    int64_t mt;
-    {
-        int64_t lo = 0, hi = -1, step = 1, cand = 1;
-        while (true) {
-            const bool ok = ok32(cand);
-            if (hi < 0) {
-                if (ok) {
-                    hi = cand;
-                } else {
-                    lo = cand;
-                    if (cand >= cap) {
-                        hi = cap;
-                        break;
-                    }
-                    cand = min(cap, lo + step);
-                    step *= 2;
-                    continue;
-                }
-            } else if (ok) {
-                hi = cand;
-            } else {
-                lo = cand;
-            }
-            if (hi - lo <= 1) break;
-            cand = lo + (hi - lo) / 2;
-        }
-        mt = hi;
-    }
 
     // ---- FP64 confirmation of mt (SD_mt <= delta < SD_{mt-1}); otherwise an
     //      exact FP64 gallop + bisection from mt, then a final evaluation
@@ -859,7 +992,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
             I->sd = sd_m;
             I->sd_prev = sd_p;
             I->flags = flags;
-            I->reserved = 0;
+            I->evals = (n32 & 0xffffu) | (n64 << 16);
         }
     }
 }
@@ -889,7 +1022,7 @@ __global__ void k_finalize(SigState* __restrict__ st, int B, int max_imfs, int32
             I->sd = 0.0;
             I->sd_prev = 0.0;
             I->flags = 0;
-            I->reserved = 0;
+            I->evals = 0;
         }
     }
 }
@@ -903,6 +1036,8 @@ __global__ void k_reset_state(SigState* __restrict__ st, int B)
     z.sd = z.sd_prev = 0.0;
     z.mean = z.maxabs = 0.0;
     z.pscale = 1.0;
+    z.kmin = dkey(INFINITY);
+    z.kmax = dkey(-INFINITY);
     z.active = 1;
     z.n_imfs = 0;
     z.stop_reason = 0;

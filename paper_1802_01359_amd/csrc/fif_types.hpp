@@ -6,6 +6,8 @@ namespace fif {
 
 // Largest complex FP64 FFT held in one workgroup's LDS (128 KiB).
 constexpr int kFftCap = 8192;
+// Elements of one four-step tile (64 KiB of LDS: two workgroups per CU).
+constexpr int kTileCap = 4096;
 // Threads of the FFT workgroups and of the scan workgroups.
 constexpr int kFftThreads = 512;
 constexpr int kScanThreads = 1024;
@@ -48,9 +50,9 @@ struct SigDesc {
 };
 
 // Ordered summary of a run of consecutive samples: enough to count sign
-// changes of nonzero forward differences across runs, plus min/max/sum.
+// changes of nonzero forward differences across runs.
 struct RunState {
-    double first, last, mn, mx, sum;
+    double first, last;
     int32_t cnt;
     int8_t fs, ls, empty, nonfinite;
 };
@@ -60,6 +62,9 @@ struct SigState {
     int64_t k, L, m;
     double sd, sd_prev;
     double mean, maxabs, pscale;
+    // min / max of the residual of the current outer step as order-preserving
+    // integer keys, accumulated with atomics (order independent)
+    long long kmin, kmax;
     int32_t active;                // 1 while the outer loop runs
     int32_t n_imfs;
     int32_t stop_reason;

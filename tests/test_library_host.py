@@ -64,7 +64,8 @@ def _plan_status(lib, lengths, max_imfs=4, **opt):
     ([1], {}, -1),
     ([0], {}, -1),
     ([4096, 11], {}, -2),            # prime factor 11
-    ([4096, 8192 * 8192 * 2], {}, -2),  # 2^27 does not split into two factors <= 8192
+    ([4096, 8192 * 4096], {}, -2),    # 2^25 does not split into two factors <= 4096
+    ([4099 * 2], {}, -2),              # 4099 is prime
     ([49 * 49 * 49 * 49 * 7], {}, -2),  # 7^9: no split into factors <= 8192
     ([4096], dict(mask_rule=3), -1),
     ([4096], dict(mask_rule=1, nu=-1.0), -1),
