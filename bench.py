@@ -123,6 +123,8 @@ def main():
     ap.add_argument("--cpu-signals", type=int, default=2, help="signals the CPU oracle decomposes")
     ap.add_argument("--cpu-budget", type=float, default=25.0, help="seconds of CPU oracle work at most")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run one 512 MiB device copy first (a known-size kernel to scale HBM counters by)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU; --gpus %d is not supported (signals are independent, "
@@ -142,6 +144,13 @@ def main():
     dt = torch.float32 if W["io"] == "f32" else torch.float64
     esize = 4 if W["io"] == "f32" else 8
     packed = torch.tensor(np.concatenate(sigs), dtype=dt, device="cuda")
+    if args.copy_probe:
+        src = torch.ones(1 << 27, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy probe: %d bytes read, %d bytes written" % (src.numel() * 4, dst.numel() * 4))
+        del src, dst
     total = int(packed.numel())
     J = W["max_imfs"]
     delta = W["delta"]

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -93,6 +94,13 @@ struct fif_plan {
     std::vector<SigDesc> sigs;
     std::vector<LenPlan> lens;
     std::vector<Work> w_init, w_single, w_p1, w_p2;
+    // four-step work is issued in chunks of signals whose intermediates
+    // share one buffer of at most chunk_bytes (so it can stay cache resident)
+    struct Chunk {
+        int32_t p1_begin, p1_count, p2_begin, p2_count;
+    };
+    std::vector<Chunk> chunks;
+    size_t chunk_bytes = 0;
     std::vector<int32_t> scan_small, scan_big;
     std::vector<int64_t> gscr_off;
     size_t lds_single = 0, lds_p1 = 0, lds_p2 = 0;
@@ -208,9 +216,16 @@ fif_status plan_length(int64_t N, LenPlan& lp)
         return fail(FIF_ERR_UNSUPPORTED_LENGTH, "length %lld has a prime factor > 7", (long long)N);
     lp.TC = (int32_t)largest_divisor_at_most(lp.N1, kTileCap / lp.N2);
     lp.TR = (int32_t)largest_divisor_at_most(lp.N2, kTileCap / lp.N1);
+    // mirror-paired column tiles need N1, N2 and the tile width even
+    lp.paired = (lp.N1 % 2 == 0 && lp.N2 % 2 == 0 && lp.TC % 2 == 0) ? 1 : 0;
     int64_t split = 1;
-    while (split * split < N) split *= 2;
+    int shift = 0;
+    while (split * split < N) {
+        split *= 2;
+        ++shift;
+    }
     lp.big_split = (int32_t)split;
+    lp.big_shift = shift;
     return FIF_OK;
 }
 
@@ -308,8 +323,11 @@ fif_status fif_plan_create(fif_plan** out, const int64_t* lengths, int32_t B, in
         }
     };
     for (auto& lp : p->lens) {
+        lp.invN = 1.0 / (double)lp.N;
         lp.sin_off = dcount;
         sins.push_back({dcount, lp.N});
+        dcount += lp.N / 2 + 1;
+        lp.isin_off = dcount;
         dcount += lp.N / 2 + 1;
         add_sub(lp.f1);
         if (lp.two_pass) {
@@ -325,8 +343,19 @@ fif_status fif_plan_create(fif_plan** out, const int64_t* lengths, int32_t B, in
     }
 
     // signals, work lists, workspace sizes
-    int64_t off = 0, spec = 0, inter = 0, gscr = 0;
+    int64_t off = 0, spec = 0, inter = 0, inter_max = 0, gscr = 0;
     int32_t parts = 0;
+    {
+        const char* env = getenv("FIF_CHUNK_BYTES");
+        p->chunk_bytes = env ? (size_t)strtoull(env, nullptr, 10) : 0;
+        if (p->chunk_bytes == 0) p->chunk_bytes = (size_t)1 << 62;
+    }
+    auto close_chunk = [&]() {
+        if (p->chunks.empty()) return;
+        fif_plan::Chunk& c = p->chunks.back();
+        c.p1_count = (int32_t)p->w_p1.size() - c.p1_begin;
+        c.p2_count = (int32_t)p->w_p2.size() - c.p2_begin;
+    };
     for (int32_t b = 0; b < B; ++b) {
         const int64_t N = lengths[b];
         const int32_t lid = len_id[N];
@@ -335,6 +364,14 @@ fif_status fif_plan_create(fif_plan** out, const int64_t* lengths, int32_t B, in
         d.N = N;
         d.off = off;
         d.spec_off = spec;
+        if (lp.two_pass) {
+            const size_t need = sizeof(double2) * (size_t)N;
+            if (p->chunks.empty() || (inter > 0 && sizeof(double2) * (size_t)inter + need > p->chunk_bytes)) {
+                close_chunk();
+                p->chunks.push_back({(int32_t)p->w_p1.size(), 0, (int32_t)p->w_p2.size(), 0});
+                inter = 0;
+            }
+        }
         d.inter_off = lp.two_pass ? inter : 0;
         d.len_id = lid;
         d.part_off = parts;
@@ -343,7 +380,10 @@ fif_status fif_plan_create(fif_plan** out, const int64_t* lengths, int32_t B, in
         p->sigs.push_back(d);
         off += N;
         spec += N / 2 + 1;
-        if (lp.two_pass) inter += N;
+        if (lp.two_pass) {
+            inter += N;
+            inter_max = std::max(inter_max, inter);
+        }
         parts += std::max(d.n_parts, d.n_init_parts);
         for (int32_t t = 0; t < d.n_init_parts; ++t) p->w_init.push_back({b, t});
         if (!lp.two_pass) {
@@ -364,6 +404,9 @@ fif_status fif_plan_create(fif_plan** out, const int64_t* lengths, int32_t B, in
             gscr += 3 * (N / 2);
         }
     }
+
+    close_chunk();
+    inter = inter_max;
 
     size_t ws = 0;
     p->ws_state = ws = align_up(ws, 256);
@@ -425,6 +468,7 @@ fif_status fif_plan_create(fif_plan** out, const int64_t* lengths, int32_t B, in
     for (auto& s : sins) {
         const int64_t cnt = s.second / 2 + 1;
         k_fill_sin<<<(unsigned)((cnt + 255) / 256), 256>>>(p->d_dtab + s.first, s.second, cnt);
+        k_fill_isin<<<(unsigned)((cnt + 255) / 256), 256>>>(p->d_dtab + s.first + cnt, s.second, cnt);
     }
     for (auto& r : roots) {
         if (r.count <= 0) continue;
@@ -564,15 +608,15 @@ void launch_init(const fif_plan* p, Bound& b, const T* x, hipStream_t s)
         k_single<MODE_FORWARD, T, T><<<(unsigned)p->w_single.size(), kFftThreads, p->lds_single, s>>>(A, x, nullptr,
                                                                                                      nullptr);
     }
-    if (!p->w_p1.empty()) {
-        A.work = p->d_p1;
+    for (const auto& c : p->chunks) {
+        A.work = p->d_p1 + c.p1_begin;
         {
             Timed tm(p, "pass1_fwd", s);
-            k_pass1<MODE_FORWARD, T><<<(unsigned)p->w_p1.size(), kFftThreads, p->lds_p1, s>>>(A, x);
+            k_pass1<MODE_FORWARD, T><<<(unsigned)c.p1_count, kFftThreads, p->lds_p1, s>>>(A, x);
         }
-        A.work = p->d_p2;
+        A.work = p->d_p2 + c.p2_begin;
         Timed tm(p, "pass2_fwd", s);
-        k_pass2<MODE_FORWARD, T, T><<<(unsigned)p->w_p2.size(), kFftThreads, p->lds_p2, s>>>(A, x, nullptr, nullptr);
+        k_pass2<MODE_FORWARD, T, T><<<(unsigned)c.p2_count, kFftThreads, p->lds_p2, s>>>(A, x, nullptr, nullptr);
     }
 }
 
@@ -599,15 +643,15 @@ void launch_step(const fif_plan* p, Bound& b, int t, const T* x, T* imfs, hipStr
         Timed tm(p, "single_step", s);
         k_single<MODE_STEP, T, T><<<(unsigned)p->w_single.size(), kFftThreads, p->lds_single, s>>>(A, x, imfs, nullptr);
     }
-    if (!p->w_p1.empty()) {
-        A.work = p->d_p1;
+    for (const auto& c : p->chunks) {
+        A.work = p->d_p1 + c.p1_begin;
         {
             Timed tm(p, "pass1_step", s);
-            k_pass1<MODE_STEP, T><<<(unsigned)p->w_p1.size(), kFftThreads, p->lds_p1, s>>>(A, x);
+            k_pass1<MODE_STEP, T><<<(unsigned)c.p1_count, kFftThreads, p->lds_p1, s>>>(A, x);
         }
-        A.work = p->d_p2;
+        A.work = p->d_p2 + c.p2_begin;
         Timed tm(p, "pass2_step", s);
-        k_pass2<MODE_STEP, T, T><<<(unsigned)p->w_p2.size(), kFftThreads, p->lds_p2, s>>>(A, x, imfs, nullptr);
+        k_pass2<MODE_STEP, T, T><<<(unsigned)c.p2_count, kFftThreads, p->lds_p2, s>>>(A, x, imfs, nullptr);
     }
 }
 
@@ -626,15 +670,15 @@ void launch_final(const fif_plan* p, Bound& b, const T* x, T* rem, int32_t* n_im
         k_single<MODE_REMAINDER, T, T><<<(unsigned)p->w_single.size(), kFftThreads, p->lds_single, s>>>(A, x, nullptr,
                                                                                                        rem);
     }
-    if (!p->w_p1.empty()) {
-        A.work = p->d_p1;
+    for (const auto& c : p->chunks) {
+        A.work = p->d_p1 + c.p1_begin;
         {
             Timed tm(p, "pass1_rem", s);
-            k_pass1<MODE_REMAINDER, T><<<(unsigned)p->w_p1.size(), kFftThreads, p->lds_p1, s>>>(A, x);
+            k_pass1<MODE_REMAINDER, T><<<(unsigned)c.p1_count, kFftThreads, p->lds_p1, s>>>(A, x);
         }
-        A.work = p->d_p2;
+        A.work = p->d_p2 + c.p2_begin;
         Timed tm(p, "pass2_rem", s);
-        k_pass2<MODE_REMAINDER, T, T><<<(unsigned)p->w_p2.size(), kFftThreads, p->lds_p2, s>>>(A, x, nullptr, rem);
+        k_pass2<MODE_REMAINDER, T, T><<<(unsigned)c.p2_count, kFftThreads, p->lds_p2, s>>>(A, x, nullptr, rem);
     }
 }
 

@@ -78,20 +78,76 @@ __device__ __forceinline__ RunState run_combine(const RunState& a, const RunStat
     return r;
 }
 
-__device__ __forceinline__ RunState run_shfl_down(const RunState& r, int off)
+// ---------------------------------------------------- wave-level exchange
+// ds_swizzle in bit-mask mode: lane l reads lane (l ^ XM) within its half
+// wave (XM < 32).  No address registers are needed, unlike ds_bpermute.
+template <int XM>
+__device__ __forceinline__ int swz_i(int v)
+{
+    return __builtin_amdgcn_ds_swizzle(v, 0x1F | (XM << 10));
+}
+template <int XM>
+__device__ __forceinline__ float swz(float v)
+{
+    return __int_as_float(swz_i<XM>(__float_as_int(v)));
+}
+template <int XM>
+__device__ __forceinline__ double swz(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = swz_i<XM>((int)(b & 0xffffffffLL));
+    const int hi = swz_i<XM>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ int rdl_i(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ float rdl(float v, int l) { return __int_as_float(rdl_i(__float_as_int(v), l)); }
+__device__ __forceinline__ double rdl(double v, int l)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = rdl_i((int)(b & 0xffffffffLL), l);
+    const int hi = rdl_i((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Value of r in lane (l ^ XM) (XM < 32).
+template <int XM>
+__device__ __forceinline__ RunState run_swz(const RunState& r)
 {
     RunState o;
-    o.first = __shfl_down(r.first, off);
-    o.last = __shfl_down(r.last, off);
-    o.cnt = __shfl_down(r.cnt, off);
+    o.first = swz<XM>(r.first);
+    o.last = swz<XM>(r.last);
+    o.cnt = swz_i<XM>(r.cnt);
     int packed = (int)(uint8_t)r.fs | ((int)(uint8_t)r.ls << 8) | ((int)r.empty << 16) |
                  ((int)r.nonfinite << 24);
-    packed = __shfl_down(packed, off);
+    packed = swz_i<XM>(packed);
     o.fs = (int8_t)(packed & 0xff);
     o.ls = (int8_t)((packed >> 8) & 0xff);
     o.empty = (int8_t)((packed >> 16) & 0xff);
     o.nonfinite = (int8_t)((packed >> 24) & 0xff);
     return o;
+}
+
+__device__ __forceinline__ RunState run_readlane(const RunState& r, int l)
+{
+    RunState o;
+    o.first = rdl(r.first, l);
+    o.last = rdl(r.last, l);
+    o.cnt = rdl_i(r.cnt, l);
+    int packed = (int)(uint8_t)r.fs | ((int)(uint8_t)r.ls << 8) | ((int)r.empty << 16) |
+                 ((int)r.nonfinite << 24);
+    packed = rdl_i(packed, l);
+    o.fs = (int8_t)(packed & 0xff);
+    o.ls = (int8_t)((packed >> 8) & 0xff);
+    o.empty = (int8_t)((packed >> 16) & 0xff);
+    o.nonfinite = (int8_t)((packed >> 24) & 0xff);
+    return o;
+}
+
+template <int XM>
+__device__ __forceinline__ void run_step(RunState& r, int lane)
+{
+    RunState o = run_swz<XM>(r);
+    if ((lane & (2 * XM - 1)) == 0) r = run_combine(r, o);
 }
 
 // Ordered reduction of one RunState per thread (thread order = sample
@@ -101,12 +157,13 @@ __device__ __forceinline__ RunState block_run_reduce(RunState r, RunState* sh)
 {
     constexpr int NW = NT / 64;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        RunState o = run_shfl_down(r, off);
-        if ((lane & (2 * off - 1)) == 0) r = run_combine(r, o);
-    }
-    if (lane == 0) sh[wave] = r;
+    run_step<1>(r, lane);
+    run_step<2>(r, lane);
+    run_step<4>(r, lane);
+    run_step<8>(r, lane);
+    run_step<16>(r, lane);
+    const RunState upper = run_readlane(r, 32);
+    if (lane == 0) sh[wave] = run_combine(r, upper);
     __syncthreads();
     RunState tot = run_empty();
     if (threadIdx.x == 0) {
@@ -129,18 +186,31 @@ __device__ __forceinline__ double dval(long long k)
 
 // ------------------------------------------------------------ reductions --
 
+// Butterfly sum within each half wave; equal bits in every lane of a half
+// (addition is commutative and every lane uses the same tree).
+template <typename T>
+__device__ __forceinline__ T half_wave_sum(T v)
+{
+    v += swz<16>(v);
+    v += swz<8>(v);
+    v += swz<4>(v);
+    v += swz<2>(v);
+    v += swz<1>(v);
+    return v;
+}
+
 // Sum of NV values per thread over the block; every thread gets the totals
 // (same order everywhere: deterministic).  sh: NV * NT/64 elements.
 template <typename T, int NT, int NV>
 __device__ __forceinline__ void block_sum(T* v, T* sh)
 {
     constexpr int NW = NT / 64;
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-#pragma unroll
-        for (int i = 0; i < NV; ++i) v[i] += __shfl_xor(v[i], off);
-    }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        const T h = half_wave_sum(v[i]);
+        v[i] = rdl(h, 0) + rdl(h, 32);
+    }
     if (lane == 0) {
 #pragma unroll
         for (int i = 0; i < NV; ++i) sh[NV * wave + i] = v[i];
@@ -161,11 +231,18 @@ template <int NT>
 __device__ __forceinline__ void block_minmax(double& mn, double& mx, double* sh)
 {
     constexpr int NW = NT / 64;
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        mn = fmin(mn, __shfl_xor(mn, off));
-        mx = fmax(mx, __shfl_xor(mx, off));
-    }
+    mn = fmin(mn, swz<16>(mn));
+    mx = fmax(mx, swz<16>(mx));
+    mn = fmin(mn, swz<8>(mn));
+    mx = fmax(mx, swz<8>(mx));
+    mn = fmin(mn, swz<4>(mn));
+    mx = fmax(mx, swz<4>(mx));
+    mn = fmin(mn, swz<2>(mn));
+    mx = fmax(mx, swz<2>(mx));
+    mn = fmin(mn, swz<1>(mn));
+    mx = fmax(mx, swz<1>(mx));
+    mn = fmin(rdl(mn, 0), rdl(mn, 32));
+    mx = fmax(rdl(mx, 0), rdl(mx, 32));
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) {
         sh[2 * wave] = mn;
@@ -181,29 +258,48 @@ __device__ __forceinline__ void block_minmax(double& mn, double& mx, double* sh)
 
 // ------------------------------------------------------ window spectrum --
 
-// (a * b) mod n for a*b < 2^53: the product and q*n are exact in FP64,
-// the rounded quotient is off by at most one.
-__device__ __forceinline__ int64_t mulmod53(int64_t a, int64_t b, int64_t n)
+// (a * b) mod n for a*b < 2^53 and n < 2^26: the product and q*n are exact
+// in FP64; the quotient from the rounded reciprocal is off by at most one.
+__device__ __forceinline__ int64_t mulmod53(int64_t a, int64_t b, int64_t n, double inv_n)
 {
     const double p = (double)a * (double)b;
     const double dn = (double)n;
-    const double q = floor(p / dn);
+    const double q = floor(p * inv_n);
     int64_t r = (int64_t)(p - q * dn);
     if (r < 0) r += n;
     if (r >= n) r -= n;
     return r;
 }
 
+// Window spectrum of one plan length at the current L.
+struct Lam {
+    int64_t N, Lmod;
+    double invN, invL;
+    const double* sinT;   // sin(pi u/N), u <= N/2
+    const double* isinT;  // 1/sin(pi u/N), 1 <= u <= N/2
+};
+
+__device__ __forceinline__ Lam make_lam(const LenPlan& lp, const double* dtab, int64_t L)
+{
+    Lam w;
+    w.N = lp.N;
+    w.Lmod = L % lp.N;
+    w.invN = lp.invN;
+    w.invL = 1.0 / (double)L;
+    w.sinT = dtab + lp.sin_off;
+    w.isinT = dtab + lp.isin_off;
+    return w;
+}
+
 // lambda_j = [sin(pi L j / N) / (L sin(pi j / N))]^4, the DFT of the
 // circulant column of the triangle-squared window, with L*j reduced mod N
-// exactly and both sines read from sin(pi u/N), u <= N/2.
-__device__ __forceinline__ double lambda_at(int64_t j, int64_t N, int64_t Lmod, double Ld,
-                                            const double* __restrict__ sinT)
+// exactly and both sines read from tables.
+__device__ __forceinline__ double lambda_at(int64_t j, const Lam& w)
 {
     if (j == 0) return 1.0;
-    int64_t t = mulmod53(Lmod, j, N);
-    if (t > N - t) t = N - t;
-    const double q = sinT[t] / (Ld * sinT[j]);
+    int64_t t = mulmod53(w.Lmod, j, w.N, w.invN);
+    if (t > w.N - t) t = w.N - t;
+    const double q = w.sinT[t] * w.isinT[j] * w.invL;
     const double q2 = q * q;
     return q2 * q2;
 }
@@ -240,6 +336,12 @@ __global__ void k_fill_sin(double* __restrict__ out, int64_t N, int64_t count)
     if (u < count) out[u] = sinpi((double)u / (double)N);
 }
 
+__global__ void k_fill_isin(double* __restrict__ out, int64_t N, int64_t count)
+{
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u < count) out[u] = u == 0 ? 0.0 : 1.0 / sinpi((double)u / (double)N);
+}
+
 // exp(-2 pi i k stride / den) for k < count, written at out[k]
 __global__ void k_fill_roots(double2* __restrict__ out, int64_t den, int64_t count, int64_t stride)
 {
@@ -255,7 +357,8 @@ __global__ void k_fill_roots(double2* __restrict__ out, int64_t den, int64_t cou
 template <bool INV>
 __device__ __forceinline__ double2 big_twiddle(const LenPlan& lp, const double2* __restrict__ tabs, int64_t a)
 {
-    double2 w = cmul(tabs[lp.big_hi_off + a / lp.big_split], tabs[lp.big_lo_off + a % lp.big_split]);
+    const int ai = (int)a;
+    double2 w = cmul(tabs[lp.big_hi_off + (ai >> lp.big_shift)], tabs[lp.big_lo_off + (ai & (lp.big_split - 1))]);
     if (INV) w.y = -w.y;
     return w;
 }
@@ -375,12 +478,11 @@ __global__ __launch_bounds__(kFftThreads) void k_single(StepArgs A, const InT* _
     double2* Rout = spec_in(A, buf ^ 1) + d.spec_off;
     const double invN = 1.0 / (double)N;
     const int64_t L = S->L, m = S->m;
-    const int64_t Lmod = L % N;
-    const double* sinT = A.dtab + lp.sin_off;
+    const Lam lw = make_lam(lp, A.dtab, L > 0 ? L : 1);
     for (int j = threadIdx.x; j <= nh; j += kFftThreads) {
         const double2 v = Rin[j];
         double g = 0.0;
-        if (MODE == MODE_STEP) g = gain_pow(lambda_at(j, N, Lmod, (double)L, sinT), m);
+        if (MODE == MODE_STEP) g = gain_pow(lambda_at(j, lw), m);
         lds[j] = step_input(v, false, g, invN);
         if (j != 0 && 2 * j != N) lds[N - j] = step_input(v, true, g, invN);
         if (MODE == MODE_STEP) Rout[j] = cscale(v, 1.0 - g);
@@ -414,9 +516,26 @@ __global__ __launch_bounds__(kFftThreads) void k_single(StepArgs A, const InT* _
 
 // ----------------------------------------------- four-step pass 1 (columns)
 
-// Work tile = TC consecutive columns c of the N2 x N1 view (element index
-// c + N1 * r).  Transforms each column over r (length N2), multiplies by the
-// four-step twiddle of (r', c) and writes Y[r'][c] to the intermediate.
+// Work tile = TC columns of the N2 x N1 view (element index c + N1 * r).
+// Transforms each column over r (length N2), multiplies by the four-step
+// twiddle of (r', c) and writes Y[r'][c] to the intermediate.
+//
+// Paired tiles (N1, N2, TC even): the tile holds h = TC/2 mirror units;
+// unit u >= 1 is the column pair {u, N1-u} (slots s and s+h), unit 0 is
+// {0, N1/2}.  Element (c, r) with r < N2/2 owns spectrum bin k = c + N1 r
+// (every bin below N/2 exactly once); its mirror N - k lies in the same tile
+// at (N1-c, N2-1-r) for c != 0 and at (0, N2-r) for c = 0; bin N/2 sits at
+// (0, N2/2).  Each bin is then read once and its gain computed once.
+// Otherwise tiles are TC consecutive columns and each element reads its bin.
+__device__ __forceinline__ int pass1_col(const LenPlan& lp, int tile, int s)
+{
+    if (!lp.paired) return tile * lp.TC + s;
+    const int h = lp.TC >> 1;
+    const int u = tile * h + (s < h ? s : s - h);
+    if (s < h) return u;
+    return u == 0 ? (lp.N1 >> 1) : lp.N1 - u;
+}
+
 template <int MODE, typename InT>
 __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __restrict__ x)
 {
@@ -426,7 +545,6 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
     const LenPlan& lp = A.lens[d.len_id];
     const int64_t N = d.N;
     const int N1 = lp.N1, N2 = lp.N2, TC = lp.TC;
-    const int c0 = w.tile * TC;
     SigState* S = A.st + w.sig;
     if (MODE == MODE_STEP && !S->active) return;
     if (MODE == MODE_REMAINDER && S->status != 0) return;
@@ -434,9 +552,9 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
     const FastDiv ftc = fastdiv(TC);
     if (MODE == MODE_FORWARD) {
         for (int f = threadIdx.x; f < total; f += kFftThreads) {
-            int cl;
-            const int r = fdivmod(f, ftc, cl);
-            lds[f] = make_double2((double)x[d.off + c0 + cl + (int64_t)N1 * r], 0.0);
+            int s;
+            const int r = fdivmod(f, ftc, s);
+            lds[f] = make_double2((double)x[d.off + pass1_col(lp, w.tile, s) + (int64_t)N1 * r], 0.0);
         }
     } else {
         const int buf = (MODE == MODE_STEP) ? (A.t & 1) : S->final_buf;
@@ -444,20 +562,52 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
         double2* Rout = spec_in(A, buf ^ 1) + d.spec_off;
         const double invN = 1.0 / (double)N;
         const int64_t L = S->L, m = S->m;
-        const int64_t Lmod = L % N;
-        const double* sinT = A.dtab + lp.sin_off;
-        const int64_t nh = N / 2;
-        for (int f = threadIdx.x; f < total; f += kFftThreads) {
-            int cl;
-            const int r = fdivmod(f, ftc, cl);
-            const int64_t k = c0 + cl + (int64_t)N1 * r;
-            const bool mirror = k > nh;
-            const int64_t j = mirror ? N - k : k;
-            const double2 v = Rin[j];
-            double g = 0.0;
-            if (MODE == MODE_STEP) g = gain_pow(lambda_at(j, N, Lmod, (double)L, sinT), m);
-            lds[f] = step_input(v, mirror, g, invN);
-            if (MODE == MODE_STEP && !mirror) Rout[j] = cscale(v, 1.0 - g);
+        const Lam lw = make_lam(lp, A.dtab, L > 0 ? L : 1);
+        if (lp.paired) {
+            const int h = TC >> 1;
+            const int owners = TC * (N2 >> 1);
+            for (int f = threadIdx.x; f <= owners; f += kFftThreads) {
+                int s, r;
+                if (f < owners) {
+                    r = fdivmod(f, ftc, s);
+                } else {
+                    if (w.tile != 0) break;
+                    s = 0;          // bin N/2 at (0, N2/2)
+                    r = N2 >> 1;
+                }
+                const int c = pass1_col(lp, w.tile, s);
+                const int64_t k = c + (int64_t)N1 * r;
+                const double2 v = Rin[k];
+                double g = 0.0;
+                if (MODE == MODE_STEP) g = gain_pow(lambda_at(k, lw), m);
+                lds[r * TC + s] = step_input(v, false, g, invN);
+                if (f < owners) {
+                    int ms, mr;
+                    if (c == 0) {
+                        ms = s;
+                        mr = (N2 - r) % N2;
+                    } else {
+                        ms = (s == h && w.tile == 0) ? s : (s < h ? s + h : s - h);
+                        mr = N2 - 1 - r;
+                    }
+                    if (!(c == 0 && r == 0)) lds[mr * TC + ms] = step_input(v, true, g, invN);
+                }
+                if (MODE == MODE_STEP) Rout[k] = cscale(v, 1.0 - g);
+            }
+        } else {
+            const int64_t nh = N / 2;
+            for (int f = threadIdx.x; f < total; f += kFftThreads) {
+                int s;
+                const int r = fdivmod(f, ftc, s);
+                const int64_t k = pass1_col(lp, w.tile, s) + (int64_t)N1 * r;
+                const bool mirror = k > nh;
+                const int64_t j = mirror ? N - k : k;
+                const double2 v = Rin[j];
+                double g = 0.0;
+                if (MODE == MODE_STEP) g = gain_pow(lambda_at(j, lw), m);
+                lds[f] = step_input(v, mirror, g, invN);
+                if (MODE == MODE_STEP && !mirror) Rout[j] = cscale(v, 1.0 - g);
+            }
         }
     }
     __syncthreads();
@@ -467,9 +617,9 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
         lds_fft<true, kTileCap>(lds, lp.f1, TC, A.ctab);
     double2* Y = A.inter + d.inter_off;
     for (int f = threadIdx.x; f < total; f += kFftThreads) {
-        int cl;
-        const int rp = fdivmod(f, ftc, cl);
-        const int c = c0 + cl;
+        int s;
+        const int rp = fdivmod(f, ftc, s);
+        const int c = pass1_col(lp, w.tile, s);
         const int64_t a = (int64_t)rp * c;
         double2 v = lds[f];
         if (a != 0) {
@@ -688,10 +838,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
     const int64_t L = sh_i[0];
     if (L < 0) return;
 
-    const int64_t nh = N / 2;
-    const int64_t Lmod = L % N;
-    const double Ld = (double)L;
-    const double* sinT = A.dtab + lp.sin_off;
+    const int nh = (int)(N / 2);
+    const Lam lw = make_lam(lp, A.dtab, L);
     const double2* R = ((A.t & 1) ? A.spec1 : A.spec0) + d.spec_off;
     const double pscale = sh_d[0];
     const double delta = A.delta;
@@ -706,11 +854,11 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
     float tau_r[NR], b_r[NR];
     extern __shared__ float lds_a[];
     float* gs = (BPT == 0) ? (A.gscr + A.gscr_off[s]) : nullptr;
-    auto weight = [&](int64_t j) -> double { return (2 * j == N) ? 1.0 : 2.0; };
-    auto sweep_bin = [&](int64_t j, float& tau, float& av, float& bv) {
+    auto weight = [&](int j) -> double { return (2 * (int64_t)j == N) ? 1.0 : 2.0; };
+    auto sweep_bin = [&](int j, float& tau, float& av, float& bv) {
         const double2 v = R[j];
         const double P = weight(j) * (v.x * v.x + v.y * v.y) * pscale;
-        const double lam = lambda_at(j, N, Lmod, Ld, sinT);
+        const double lam = lambda_at(j, lw);
         const float lf = (float)lam;
         bv = (float)P;
         av = (float)(P * lam * lam);
@@ -719,15 +867,17 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
     if (BPT > 0) {
 #pragma unroll
         for (int i = 0; i < NR; ++i) {
-            const int64_t j = 1 + tid + (int64_t)i * T;
+            const int j = 1 + tid + i * T;
             float av = 0.f;
             tau_r[i] = 0.f;
             b_r[i] = 0.f;
             if (j <= nh) sweep_bin(j, tau_r[i], av, b_r[i]);
             lds_a[i * T + tid] = av;
+            // keep the FP64 work of different bins apart (register pressure)
+            __builtin_amdgcn_sched_barrier(0);
         }
     } else {
-        for (int64_t j = 1 + tid; j <= nh; j += T) {
+        for (int j = 1 + tid; j <= nh; j += T) {
             float tau, av, bv;
             sweep_bin(j, tau, av, bv);
             gs[3 * (j - 1)] = tau;
@@ -758,7 +908,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
                     v[1] += b_r[i];
                 }
             } else {
-                for (int64_t j = 1 + tid; j <= nh; j += T) {
+                for (int j = 1 + tid; j <= nh; j += T) {
                     v[0] += gs[3 * (j - 1) + 1];
                     v[1] += gs[3 * (j - 1) + 2];
                 }
@@ -767,7 +917,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
 #pragma unroll
             for (int i = 0; i < NR; ++i) acc_bin(tau_r[i], lds_a[i * T + tid], b_r[i], e, v[0], v[1]);
         } else {
-            for (int64_t j = 1 + tid; j <= nh; j += T)
+            for (int j = 1 + tid; j <= nh; j += T)
                 acc_bin(gs[3 * (j - 1)], gs[3 * (j - 1) + 1], gs[3 * (j - 1) + 2], e, v[0], v[1]);
         }
         if (m == 1 && tid == 0) {
@@ -849,10 +999,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
     auto sd64 = [&](int64_t m, double& sd_m, double& sd_mm1) {
         double v[4] = {0.0, 0.0, 0.0, 0.0};
         const int64_t e = m - 2;  // exponent of mu at m-1; may be -1
-        for (int64_t j = 1 + tid; j <= nh; j += T) {
+        for (int j = 1 + tid; j <= nh; j += T) {
             const double2 z = R[j];
             const double P = weight(j) * (z.x * z.x + z.y * z.y) * pscale;
-            const double lam = lambda_at(j, N, Lmod, Ld, sinT);
+            const double lam = lambda_at(j, lw);
             const double l2 = lam * lam;
             const double om = 1.0 - lam;
             double xe;  // mu^e

@@ -10,9 +10,9 @@ constexpr int kFftCap = 8192;
 constexpr int kTileCap = 4096;
 // Threads of the FFT workgroups and of the scan workgroups.
 constexpr int kFftThreads = 512;
-constexpr int kScanThreads = 1024;
+constexpr int kScanThreads = 512;
 // Spectrum bins a scan thread keeps in registers (fast path: N <= 65536).
-constexpr int kScanBinsPerThread = 32;
+constexpr int kScanBinsPerThread = 64;
 constexpr int kMaxRadices = 24;
 
 // Radix plan of one LDS-resident complex FFT of length n.
@@ -29,12 +29,16 @@ struct LenPlan {
     int32_t two_pass;              // 0: single LDS pass; 1: N = N1 * N2 four-step
     int32_t N1, N2;                // N1: pass-2 length (columns), N2: pass-1 length (rows)
     int32_t TC, TR;                // pass-1 column tile, pass-2 row tile
+    int32_t paired;                // pass-1 tiles hold mirror column pairs {c, N1-c}
+    int32_t pad0;
     SubFft f1;                     // length N2 (pass 1) or N (single pass)
     SubFft f2;                     // length N1 (pass 2)
     int64_t sin_off;               // offset (doubles) of sin(pi u/N), u = 0..N/2
+    int64_t isin_off;              // offset (doubles) of 1/sin(pi u/N), u = 1..N/2
     int64_t big_lo_off, big_hi_off;// offsets (complex) of the four-step twiddle tables
-    int32_t big_split;             // exp(-2 pi i a/N) = hi[a / split] * lo[a % split]
-    int32_t pad;
+    double invN;                   // 1/N rounded
+    int32_t big_split;             // exp(-2 pi i a/N) = hi[a >> shift] * lo[a & (split-1)]
+    int32_t big_shift;             // log2(big_split)
 };
 
 // Per signal of the batch.
