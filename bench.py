@@ -68,35 +68,46 @@ def src_digest() -> str:
     return h.hexdigest()[:16]
 
 
+SINGLE_MAX = 8192          # longest signal handled by one LDS pass
+SCAN_REG_BINS = 32768      # most bins the one-workgroup scan keeps resident
+
+
 def algorithmic_bytes(kind: str, lengths, n_imfs, max_imfs: int, esize: int) -> float:
     """Bytes a kernel kind must move per call of the whole decomposition, by
     the data flow of the path (not by its implementation): half spectra are
-    (N/2+1) complex FP64 bins, signals/IMFs/remainders esize bytes/sample."""
+    (N/2+1) complex FP64 bins, signals/IMFs/remainders esize bytes/sample.
+    Each kind counts only the signals it handles."""
     L = np.asarray(lengths, dtype=np.float64)
     n = np.asarray(n_imfs)
     spec = (np.floor(L / 2) + 1) * 16.0
-    if kind in ("pass1_step", "single_step", "scan"):
-        act = sum(float(np.sum(spec[n > t])) for t in range(max_imfs))
-        if kind == "scan":
-            return act                                  # read the residual spectrum
-        if kind == "pass1_step":
-            return 2.0 * act                            # read + write the spectrum
-        return 2.0 * act + max_imfs * float(np.sum(L)) * esize
+    single = L <= SINGLE_MAX
+    sel = {"single": single, "pass1": ~single, "pass2": ~single,
+           "scan": np.floor(L / 2) <= SCAN_REG_BINS, "scan_big": np.floor(L / 2) > SCAN_REG_BINS}
+    fam = kind.split("_")[0] if not kind.startswith("scan") else kind
+    msk = sel.get(fam, np.ones_like(single))
+    Ls, sp, ns = L[msk], spec[msk], n[msk]
+    act = sum(float(np.sum(sp[ns > t])) for t in range(max_imfs))
+    if kind in ("scan", "scan_big"):
+        return act                                          # read the residual spectrum
+    if kind == "pass1_step":
+        return 2.0 * act                                    # read + write the spectrum
     if kind == "pass2_step":
-        return max_imfs * float(np.sum(L)) * esize      # IMF rows (zeros once stopped)
+        return max_imfs * float(np.sum(Ls)) * esize         # IMF rows (zeros once stopped)
+    if kind == "single_step":
+        return 2.0 * act + max_imfs * float(np.sum(Ls)) * esize
     if kind in ("pass1_fwd", "init_stats"):
-        return float(np.sum(L)) * esize
+        return float(np.sum(Ls)) * esize
     if kind == "pass2_fwd":
-        return float(np.sum(spec))
+        return float(np.sum(sp))
     if kind == "single_fwd":
-        return float(np.sum(L)) * esize + float(np.sum(spec))
-    if kind in ("pass1_rem",):
-        return float(np.sum(spec))
-    if kind in ("pass2_rem",):
-        return float(np.sum(L)) * esize
+        return float(np.sum(Ls)) * esize + float(np.sum(sp))
+    if kind == "pass1_rem":
+        return float(np.sum(sp))
+    if kind == "pass2_rem":
+        return float(np.sum(Ls)) * esize
     if kind == "single_rem":
-        return float(np.sum(spec)) + float(np.sum(L)) * esize
-    return 0.0
+        return float(np.sum(sp)) + float(np.sum(Ls)) * esize
+    return 0.0                                              # bookkeeping / implementation-only kernels
 
 
 def cpu_baseline(sigs, delta, max_imfs, want: int, budget_s: float):

@@ -77,6 +77,8 @@ typedef enum {
 /* per-IMF flags */
 #define FIF_IMF_CAP 1u          /* inner count stopped at max_inner, SD > delta */
 #define FIF_IMF_REFINED 2u      /* FP64 verification moved the FP32 estimate of m */
+#define FIF_IMF_UNRESOLVED 4u   /* the multi-workgroup search ran out of rounds; m is
+                                   the smallest FP64-verified count found (not expected) */
 
 /* why a signal's outer loop ended (fif_signal_info.stop_reason) */
 #define FIF_STOP_MAX_IMFS 0

@@ -16,7 +16,7 @@
 #include <vector>
 
 #include "../../include/fif.h"
-#include "fif_kernels.hpp"
+#include "fif_bigscan.hpp"
 
 using namespace fif;
 
@@ -102,7 +102,7 @@ struct fif_plan {
     std::vector<Chunk> chunks;
     size_t chunk_bytes = 0;
     std::vector<int32_t> scan_small, scan_big;
-    std::vector<int64_t> gscr_off;
+    std::vector<Work> w_btile, w_count;
     size_t lds_single = 0, lds_p1 = 0, lds_p2 = 0;
     // device copies (one allocation)
     DevBuf dmeta, dtabs;
@@ -110,12 +110,12 @@ struct fif_plan {
     LenPlan* d_lens = nullptr;
     Work *d_init = nullptr, *d_single = nullptr, *d_p1 = nullptr, *d_p2 = nullptr;
     int32_t *d_scan_small = nullptr, *d_scan_big = nullptr;
-    int64_t* d_gscr_off = nullptr;
+    Work *d_btile = nullptr, *d_count = nullptr;
     double* d_dtab = nullptr;
     double2* d_ctab = nullptr;
     // workspace layout (byte offsets)
     size_t ws_state = 0, ws_spec0 = 0, ws_spec1 = 0, ws_inter = 0, ws_parts = 0, ws_psum = 0, ws_gscr = 0,
-           ws_total = 0;
+           ws_bigs = 0, ws_bpart = 0, ws_resid = 0, ws_total = 0;
     // kernel timing (fif_plan_profile)
     struct Rec {
         int kind;
@@ -343,8 +343,8 @@ fif_status fif_plan_create(fif_plan** out, const int64_t* lengths, int32_t B, in
     }
 
     // signals, work lists, workspace sizes
-    int64_t off = 0, spec = 0, inter = 0, inter_max = 0, gscr = 0;
-    int32_t parts = 0;
+    int64_t off = 0, spec = 0, inter = 0, inter_max = 0, gscr = 0, resid = 0;
+    int32_t parts = 0, nbig = 0, btiles = 0;
     {
         const char* env = getenv("FIF_CHUNK_BYTES");
         p->chunk_bytes = env ? (size_t)strtoull(env, nullptr, 10) : 0;
@@ -375,8 +375,26 @@ fif_status fif_plan_create(fif_plan** out, const int64_t* lengths, int32_t B, in
         d.inter_off = lp.two_pass ? inter : 0;
         d.len_id = lid;
         d.part_off = parts;
-        d.n_parts = lp.two_pass ? (int32_t)(N / lp.TR) : 1;
         d.n_init_parts = (int32_t)((N + kFftCap - 1) / kFftCap);
+        // run summaries per row tile, unless that would make too many of them:
+        // then pass 2 writes the FP64 residual and k_count_resid summarizes it
+        const bool use_resid = lp.two_pass && (N / lp.TR) > 65536;
+        d.resid_off = use_resid ? resid : -1;
+        if (use_resid) resid += N;
+        d.n_parts = !lp.two_pass ? 1 : (use_resid ? d.n_init_parts : (int32_t)(N / lp.TR));
+        d.bs = -1;
+        d.bt_off = 0;
+        d.n_btiles = 0;
+        d.gs_off = 0;
+        d.pad = 0;
+        if (N / 2 > (int64_t)kScanBinsPerThread * kScanThreads) {
+            d.bs = nbig++;
+            d.bt_off = btiles;
+            d.n_btiles = (int32_t)((N / 2 + kBigTile - 1) / kBigTile);
+            btiles += d.n_btiles;
+            d.gs_off = gscr;
+            gscr += 3 * (N / 2);
+        }
         p->sigs.push_back(d);
         off += N;
         spec += N / 2 + 1;
@@ -386,6 +404,9 @@ fif_status fif_plan_create(fif_plan** out, const int64_t* lengths, int32_t B, in
         }
         parts += std::max(d.n_parts, d.n_init_parts);
         for (int32_t t = 0; t < d.n_init_parts; ++t) p->w_init.push_back({b, t});
+        if (use_resid)
+            for (int32_t t = 0; t < d.n_init_parts; ++t) p->w_count.push_back({b, t});
+        for (int32_t t = 0; t < d.n_btiles; ++t) p->w_btile.push_back({b, t});
         if (!lp.two_pass) {
             p->w_single.push_back({b, 0});
             p->lds_single = std::max(p->lds_single, (size_t)N * sizeof(double2));
@@ -395,14 +416,10 @@ fif_status fif_plan_create(fif_plan** out, const int64_t* lengths, int32_t B, in
             p->lds_p1 = std::max(p->lds_p1, (size_t)lp.TC * lp.N2 * sizeof(double2));
             p->lds_p2 = std::max(p->lds_p2, (size_t)lp.TR * lp.N1 * sizeof(double2));
         }
-        if (N / 2 <= (int64_t)kScanBinsPerThread * kScanThreads) {
+        if (d.bs < 0)
             p->scan_small.push_back(b);
-            p->gscr_off.push_back(-1);
-        } else {
+        else
             p->scan_big.push_back(b);
-            p->gscr_off.push_back(gscr);
-            gscr += 3 * (N / 2);
-        }
     }
 
     close_chunk();
@@ -423,6 +440,12 @@ fif_status fif_plan_create(fif_plan** out, const int64_t* lengths, int32_t B, in
     ws += sizeof(double) * (size_t)parts;
     p->ws_gscr = ws = align_up(ws, 256);
     ws += sizeof(float) * (size_t)gscr;
+    p->ws_bigs = ws = align_up(ws, 256);
+    ws += sizeof(BigScan) * (size_t)nbig;
+    p->ws_bpart = ws = align_up(ws, 256);
+    ws += sizeof(double) * 2 * kBigCand * (size_t)btiles;
+    p->ws_resid = ws = align_up(ws, 256);
+    ws += sizeof(double) * (size_t)resid;
     p->ws_total = align_up(ws, 256);
 
     // metadata upload
@@ -443,8 +466,10 @@ fif_status fif_plan_create(fif_plan** out, const int64_t* lengths, int32_t B, in
     mo += sizeof(int32_t) * p->scan_small.size();
     size_t o_sb = (mo = align_up(mo, 256));
     mo += sizeof(int32_t) * p->scan_big.size();
-    size_t o_go = (mo = align_up(mo, 256));
-    mo += sizeof(int64_t) * p->gscr_off.size();
+    size_t o_bt = (mo = align_up(mo, 256));
+    mo += sizeof(Work) * p->w_btile.size();
+    size_t o_ct = (mo = align_up(mo, 256));
+    mo += sizeof(Work) * p->w_count.size();
     mo = align_up(mo, 256);
     std::vector<char> host(mo, 0);
     if (hipMalloc(&p->dmeta.p, mo) != hipSuccess) return fail(FIF_ERR_NOMEM, "plan metadata allocation failed");
@@ -457,7 +482,8 @@ fif_status fif_plan_create(fif_plan** out, const int64_t* lengths, int32_t B, in
     p->d_p2 = upload(db, o_p2, p->w_p2, host);
     p->d_scan_small = upload(db, o_ss, p->scan_small, host);
     p->d_scan_big = upload(db, o_sb, p->scan_big, host);
-    p->d_gscr_off = upload(db, o_go, p->gscr_off, host);
+    p->d_btile = upload(db, o_bt, p->w_btile, host);
+    p->d_count = upload(db, o_ct, p->w_count, host);
     HIP_TRY(hipMemcpy(p->dmeta.p, host.data(), mo, hipMemcpyHostToDevice));
 
     // tables, computed on the device in FP64
@@ -564,6 +590,7 @@ Bound bind(const fif_plan* p, void* ws, double delta, fif_imf_info* info)
     A.spec1 = (double2*)(w + p->ws_spec1);
     A.inter = (double2*)(w + p->ws_inter);
     A.parts = (RunState*)(w + p->ws_parts);
+    A.resid = (double*)(w + p->ws_resid);
     A.t = 0;
     A.max_imfs = p->max_imfs;
     ScanArgs& S = b.sc;
@@ -577,7 +604,8 @@ Bound bind(const fif_plan* p, void* ws, double delta, fif_imf_info* info)
     S.spec0 = A.spec0;
     S.spec1 = A.spec1;
     S.gscr = (float*)(w + p->ws_gscr);
-    S.gscr_off = p->d_gscr_off;
+    S.bigs = (BigScan*)(w + p->ws_bigs);
+    S.bpart = (double*)(w + p->ws_bpart);
     S.info = info;
     S.t = 0;
     S.max_imfs = p->max_imfs;
@@ -632,9 +660,17 @@ void launch_step(const fif_plan* p, Bound& b, int t, const T* x, T* imfs, hipStr
                                      sizeof(float) * kScanBinsPerThread * kScanThreads, s>>>(S);
     }
     if (!p->scan_big.empty()) {
-        S.list = p->d_scan_big;
         Timed tm(p, "scan_big", s);
-        k_scan<0><<<(unsigned)p->scan_big.size(), kScanThreads, 0, s>>>(S);
+        S.list = p->d_scan_big;
+        const unsigned nb = (unsigned)p->scan_big.size(), nt = (unsigned)p->w_btile.size();
+        k_bscan_prep<kScanThreads><<<nb, kScanThreads, 0, s>>>(S);
+        k_bscan_round<kScanThreads, true><<<nt, kScanThreads, 0, s>>>(S, p->d_btile);
+        k_bscan_decide<<<nb, 64 * kDecideGroups, 0, s>>>(S);
+        for (int r = 0; r < kBigRounds; ++r) {
+            k_bscan_round<kScanThreads, false><<<nt, kScanThreads, 0, s>>>(S, p->d_btile);
+            k_bscan_decide<<<nb, 64 * kDecideGroups, 0, s>>>(S);
+        }
+        k_bscan_final<kScanThreads><<<nb, 64, 0, s>>>(S);
     }
     StepArgs A = b.sa;
     A.t = t;
@@ -652,6 +688,11 @@ void launch_step(const fif_plan* p, Bound& b, int t, const T* x, T* imfs, hipStr
         A.work = p->d_p2 + c.p2_begin;
         Timed tm(p, "pass2_step", s);
         k_pass2<MODE_STEP, T, T><<<(unsigned)c.p2_count, kFftThreads, p->lds_p2, s>>>(A, x, imfs, nullptr);
+    }
+    if (!p->w_count.empty()) {
+        Timed tm(p, "count_resid", s);
+        k_count_resid<<<(unsigned)p->w_count.size(), kFftThreads, 0, s>>>(p->d_sigs, p->d_count, A.resid, A.parts,
+                                                                           A.st);
     }
 }
 

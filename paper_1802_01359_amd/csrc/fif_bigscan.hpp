@@ -1,0 +1,446 @@
+// Search for m when a signal has more spectrum bins than one workgroup holds
+// (N/2 > kScanBinsPerThread * kScanThreads).  Same mathematics as k_scan
+// (smallest m with SD_m <= delta, SD by Parseval, FP32 bracketing then FP64
+// confirmation), spread over tiles of kBigTile bins:
+//
+//   k_bscan_prep   one workgroup per signal: run summaries, stop rules, L,
+//                  power scale, the geometric candidates m = 1, 2, 4, ...
+//   k_bscan_round<SWEEP = true>  per tile: FP32 copies (log2 mu,
+//                  power*lambda^2, power) to scratch, then the first round
+//   k_bscan_round  per tile, a fixed number of launches: partial sums of the
+//                  current candidates (FP32 from scratch, or FP64 from the
+//                  spectrum in the confirmation phase)
+//   k_bscan_final  writes L, m, SD and the IMF record
+//
+//   k_bscan_decide one small workgroup per signal after every round: adds the
+//                  per-tile partial sums in tile order and picks the next
+//                  candidates -- evenly spaced inside the bracket, or a
+//                  gallop when no candidate satisfies the test yet.
+// Signals already decided skip the remaining launches.  Partial sums cross
+// workgroups only through kernel boundaries (no device-scope fences).
+#pragma once
+#include "fif_kernels.hpp"
+
+namespace fif {
+
+// geometric probes 1, 2, 4, 8, ...
+__device__ __forceinline__ int64_t geo_next(int64_t m) { return m * 2; }
+
+// Evenly spaced candidates strictly inside (lo, hi), at most kBigRefine: the
+// exponentials per bin grow with the candidates per round while the rounds
+// fall only with their logarithm.
+__device__ __forceinline__ void fill_inside(BigScan* G, int64_t lo, int64_t hi)
+{
+    const int64_t gap = hi - lo - 1;
+    const int n = (int)min((int64_t)kBigRefine, gap);
+    for (int i = 0; i < n; ++i) G->cand[i] = lo + ((int64_t)(i + 1) * (hi - lo)) / (n + 1);
+    // strictly increasing and inside (lo, hi) because (hi - lo) >= n + 1
+    G->ncand = n;
+}
+
+// Gallop from lo (SD_lo > delta known): lo + 1, lo + 2, lo + 4, ... capped.
+__device__ __forceinline__ void fill_gallop(BigScan* G, int64_t lo, int64_t cap)
+{
+    int n = 0;
+    int64_t step = 1;
+    while (n < kBigCand) {
+        const int64_t c = min(cap, lo + step);
+        if (n > 0 && c == G->cand[n - 1]) break;
+        G->cand[n++] = c;
+        if (c == cap) break;
+        step *= 2;
+    }
+    G->ncand = n;
+}
+
+template <int T>
+__global__ __launch_bounds__(T) void k_bscan_prep(ScanArgs A)
+{
+    __shared__ RunState shr[T / 64];
+    __shared__ int64_t sh_i[2];
+    __shared__ double sh_d[1];
+    const int s = A.list[blockIdx.x];
+    const SigDesc d = A.sigs[s];
+    SigState* S = A.st + s;
+    BigScan* G = A.bigs + d.bs;
+    if (!S->active) {
+        if (threadIdx.x == 0) G->phase = kBigInactive;
+        return;
+    }
+    scan_prologue<T>(A, s, d, S, shr, sh_i, sh_d);
+    if (threadIdx.x == 0) {
+        const int64_t L = sh_i[0];
+        if (L < 0) {
+            G->phase = kBigInactive;
+        } else {
+            G->phase = 0;
+            G->L = L;
+            G->pscale = sh_d[0];
+            G->n32 = G->n64 = 0;
+            G->flags = 0;
+            G->lo = 0;
+            G->hi = -1;
+            G->elo = 0;
+            G->ehi = -1;
+            G->sd_lo = INFINITY;
+            G->sd_hi = 0.0;
+            const int64_t cap = A.max_inner;
+            int n = 0;
+            for (int64_t m = 1; m < cap && n < kBigCand - 1; m = geo_next(m)) G->cand[n++] = m;
+            G->cand[n++] = cap;
+            G->ncand = n;
+        }
+    }
+}
+
+// Partial sums of the current candidates over this tile's bins, left in
+// out[2i] = sum a x, out[2i+1] = sum b x (shared memory, all threads).
+// FP32 phases: x = 2^((m-1) tau) from scratch; FP64 phase: mu^(m-1) from the
+// spectrum with FP64 lambda, two candidates at a time.
+template <int T, int BPT>
+__device__ __forceinline__ void bscan_tile_sums(const ScanArgs& A, const SigDesc& d, const LenPlan& lp,
+                                                const BigScan* G, int tile, double* out, float* shf,
+                                                double* shd)
+{
+    const int tid = threadIdx.x;
+    const int nh = (int)(d.N / 2);
+    const int j0 = 1 + tile * kBigTile;
+    const int ph = G->phase;
+    const int nc = G->ncand;
+    const double2* R = ((A.t & 1) ? A.spec1 : A.spec0) + d.spec_off;
+    if (ph < 2) {
+        const float* tau = A.gscr + d.gs_off;
+        const float* av = tau + nh;
+        const float* bv = av + nh;
+        float e[kBigCand];
+#pragma unroll
+        for (int i = 0; i < kBigCand; ++i) e[i] = (i < nc) ? (float)(G->cand[i] - 1) : 0.f;
+        float acc[2 * kBigCand];
+#pragma unroll
+        for (int i = 0; i < 2 * kBigCand; ++i) acc[i] = 0.f;
+        for (int q = 0; q < BPT; ++q) {
+            const int j = j0 + tid + q * T;
+            if (j > nh) break;
+            const float tj = tau[j - 1], aj = av[j - 1], bj = bv[j - 1];
+#pragma unroll
+            for (int i = 0; i < kBigCand; ++i) {
+                if (i < nc) {
+                    const float x = (e[i] == 0.f) ? 1.f : __builtin_amdgcn_exp2f(e[i] * tj);
+                    acc[2 * i] += aj * x;
+                    acc[2 * i + 1] += bj * x;
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < kBigCand; c += 4) {
+            if (c < nc) {
+                float v8[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) v8[k] = acc[2 * c + k];
+                block_sum<float, T, 8>(v8, shf);
+                if (tid == 0) {
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) out[2 * c + k] = (double)v8[k];
+                }
+            }
+        }
+    } else {
+        const Lam lw = make_lam(lp, A.dtab, G->L);
+        const double pscale = G->pscale;
+        for (int c = 0; c < nc; c += 2) {
+            const int64_t e0 = G->cand[c] - 1;
+            const int64_t e1 = (c + 1 < nc) ? G->cand[c + 1] - 1 : -1;
+            double acc[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int q = 0; q < BPT; ++q) {
+                const int j = j0 + tid + q * T;
+                if (j > nh) break;
+                const double2 z = R[j];
+                const double P = ((2 * (int64_t)j == d.N) ? 1.0 : 2.0) * (z.x * z.x + z.y * z.y) * pscale;
+                const double lam = lambda_at(j, lw);
+                const double l2 = lam * lam;
+                const double mu = (1.0 - lam) * (1.0 - lam);
+                double x0, x1 = 0.0;
+                if (lam >= 1.0) {
+                    x0 = (e0 == 0) ? 1.0 : 0.0;
+                    x1 = (e1 == 0) ? 1.0 : 0.0;
+                } else {
+                    x0 = (e0 <= kPowByMul) ? ipow(mu, e0) : exp((double)e0 * 2.0 * log1p(-lam));
+                    if (e1 == e0 + 1)
+                        x1 = x0 * mu;
+                    else if (e1 >= 0)
+                        x1 = (e1 <= kPowByMul) ? ipow(mu, e1) : exp((double)e1 * 2.0 * log1p(-lam));
+                }
+                acc[0] += P * l2 * x0;
+                acc[1] += P * x0;
+                acc[2] += P * l2 * x1;
+                acc[3] += P * x1;
+            }
+            block_sum<double, T, 4>(acc, shd);
+            if (tid == 0) {
+                out[2 * c] = acc[0];
+                out[2 * c + 1] = acc[1];
+                if (c + 1 < nc) {
+                    out[2 * c + 2] = acc[2];
+                    out[2 * c + 3] = acc[3];
+                }
+            }
+        }
+    }
+    // DC bin (lambda_0 = 1): contributes to m = 1 only
+    if (tile == 0 && tid == 0) {
+        const double P0 = (R[0].x * R[0].x + R[0].y * R[0].y) * G->pscale;
+        for (int i = 0; i < nc; ++i)
+            if (G->cand[i] == 1) {
+                out[2 * i] += P0;
+                out[2 * i + 1] += P0;
+            }
+    }
+    __syncthreads();
+}
+
+// Sums over the tiles of every candidate's two partial sums: tot[2i]
+// (numerator) and tot[2i+1] (denominator) of candidate i.  kDecideGroups
+// groups of 64 threads each add a contiguous range of tiles in tile order;
+// the group results are then added in group order, so the result depends
+// only on the number of tiles.
+constexpr int kDecideGroups = 16;
+static_assert(2 * kBigCand <= 64, "one lane per partial sum");
+__device__ __forceinline__ void bscan_tile_totals(const ScanArgs& A, const SigDesc& d, int nc, double* part,
+                                                  double* tot)
+{
+    const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int nt = d.n_btiles;
+    const int t0 = (int)(((int64_t)nt * g) / kDecideGroups), t1 = (int)(((int64_t)nt * (g + 1)) / kDecideGroups);
+    double s = 0.0;
+    if (c < 2 * nc) {
+        const double* P = A.bpart + (int64_t)d.bt_off * 2 * kBigCand + c;
+#pragma unroll 8
+        for (int t = t0; t < t1; ++t) s += P[(int64_t)t * 2 * kBigCand];
+    }
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (g == 0) {
+        double v = 0.0;
+        for (int q = 0; q < kDecideGroups; ++q) v += part[q * 64 + c];
+        tot[c] = v;
+    }
+}
+
+// Thread 0 of the decide workgroup: update the brackets, choose the next
+// candidates.
+__device__ __forceinline__ void bscan_decide(const ScanArgs& A, const SigDesc& d, BigScan* G, const double* tot)
+{
+    const int nc = G->ncand;
+    const double* Asum = tot;          // numerator of candidate i at Asum[2i]
+    const double* Bsum = tot + 1;      // denominator at Bsum[2i]
+    const double delta = A.delta;
+    const int64_t cap = A.max_inner;
+    if (G->phase < 2) {
+        G->n32 += 1;
+        const double d2 = (double)(float)(delta * delta);
+        int q = -1;
+        for (int i = 0; i < nc; ++i) {
+            const bool ok = Bsum[2 * i] <= 0.0 || Asum[2 * i] <= d2 * Bsum[2 * i];
+            if (ok) {
+                q = i;
+                break;
+            }
+        }
+        int64_t lo = G->lo, hi = G->hi;
+        if (q >= 0) {
+            hi = G->cand[q];
+            if (q > 0) lo = G->cand[q - 1];
+        } else {
+            lo = G->cand[nc - 1];
+        }
+        int64_t mt = -1;
+        if (q < 0 && lo >= cap)
+            mt = cap;
+        else if (hi >= 0 && hi - lo <= 1)
+            mt = hi;
+        G->lo = lo;
+        G->hi = hi;
+        if (mt >= 0) {
+            // FP64 confirmation of SD_mt <= delta < SD_{mt-1}
+            G->phase = 2;
+            G->mt = mt;
+            if (mt == 1) {
+                G->cand[0] = 1;
+                G->ncand = 1;
+            } else {
+                G->cand[0] = mt - 1;
+                G->cand[1] = mt;
+                G->ncand = 2;
+            }
+        } else if (hi >= 0) {
+            G->phase = 1;
+            fill_inside(G, lo, hi);
+        } else {
+            G->phase = 1;
+            fill_gallop(G, lo, cap);
+        }
+        return;
+    }
+    // FP64 phase
+    G->n64 += 1;
+    int64_t elo = G->elo, ehi = G->ehi;
+    double sd_lo = G->sd_lo, sd_hi = G->sd_hi;
+    for (int i = 0; i < nc; ++i) {
+        const double sd = Bsum[2 * i] > 0.0 ? sqrt(Asum[2 * i] / Bsum[2 * i]) : 0.0;
+        const int64_t c = G->cand[i];
+        if (sd <= delta) {
+            if (ehi < 0 || c < ehi) {
+                ehi = c;
+                sd_hi = sd;
+            }
+        } else if (c > elo) {
+            elo = c;
+            sd_lo = sd;
+        }
+    }
+    if (G->n64 == 1 && !(ehi == G->mt && elo == G->mt - 1)) G->flags |= FIF_IMF_REFINED;
+    G->elo = elo;
+    G->ehi = ehi;
+    G->sd_lo = sd_lo;
+    G->sd_hi = sd_hi;
+    if (ehi >= 0 && ehi - elo <= 1) {
+        G->m = ehi;
+        G->sd_m = sd_hi;
+        G->sd_p = (ehi == 1) ? INFINITY : sd_lo;
+        G->phase = 3;
+    } else if (ehi < 0 && elo >= cap) {
+        G->m = cap;
+        G->sd_m = sd_lo;
+        G->sd_p = sd_lo;
+        G->flags |= FIF_IMF_CAP;
+        G->phase = 3;
+    } else if (ehi < 0) {
+        fill_gallop(G, elo, cap);
+    } else {
+        fill_inside(G, elo, ehi);
+    }
+}
+
+// One candidate round over one tile (first round: also fill the scratch).
+template <int T, bool SWEEP>
+__global__ __launch_bounds__(T) void k_bscan_round(ScanArgs A, const Work* __restrict__ work)
+{
+    constexpr int BPT = kBigTile / T;
+    __shared__ double shd[4 * (T / 64)];
+    __shared__ float shf[8 * (T / 64)];
+    __shared__ double shv[2 * kBigCand];
+    const Work w = work[blockIdx.x];
+    const SigDesc d = A.sigs[w.sig];
+    const LenPlan& lp = A.lens[d.len_id];
+    BigScan* G = A.bigs + d.bs;
+    const int ph = G->phase;
+    if (ph >= 3) return;
+    if (SWEEP) {
+        const int nh = (int)(d.N / 2);
+        float* tau = A.gscr + d.gs_off;
+        float* av = tau + nh;
+        float* bv = av + nh;
+        const double2* R = ((A.t & 1) ? A.spec1 : A.spec0) + d.spec_off;
+        const Lam lw = make_lam(lp, A.dtab, G->L);
+        const double pscale = G->pscale;
+        for (int q = 0; q < BPT; ++q) {
+            const int j = 1 + w.tile * kBigTile + threadIdx.x + q * T;
+            if (j > nh) break;
+            const double2 z = R[j];
+            const double P = ((2 * (int64_t)j == d.N) ? 1.0 : 2.0) * (z.x * z.x + z.y * z.y) * pscale;
+            const double lam = lambda_at(j, lw);
+            bv[j - 1] = (float)P;
+            av[j - 1] = (float)(P * lam * lam);
+            tau[j - 1] = 2.8853900817779268f * log1pf(-(float)lam);
+        }
+        // each thread reads back only its own bins below: no barrier needed
+    }
+    bscan_tile_sums<T, BPT>(A, d, lp, G, w.tile, shv, shf, shd);
+    double* P = A.bpart + ((int64_t)d.bt_off + w.tile) * 2 * kBigCand;
+    const int nc = G->ncand;
+    if (threadIdx.x < 2 * nc) P[threadIdx.x] = shv[threadIdx.x];
+}
+
+// After a round: tile totals in tile order, then the next candidates.
+__global__ __launch_bounds__(64 * kDecideGroups) void k_bscan_decide(ScanArgs A)
+{
+    __shared__ double part[64 * kDecideGroups];
+    __shared__ double tot[2 * kBigCand];
+    const int s = A.list[blockIdx.x];
+    const SigDesc d = A.sigs[s];
+    BigScan* G = A.bigs + d.bs;
+    if (G->phase >= 3) return;
+    bscan_tile_totals(A, d, G->ncand, part, tot);
+    __syncthreads();
+    if (threadIdx.x == 0) bscan_decide(A, d, G, tot);
+}
+
+template <int T>
+__global__ __launch_bounds__(T) void k_bscan_final(ScanArgs A)
+{
+    if (threadIdx.x != 0) return;
+    const int s = A.list[blockIdx.x];
+    const SigDesc d = A.sigs[s];
+    SigState* S = A.st + s;
+    BigScan* G = A.bigs + d.bs;
+    if (G->phase == kBigInactive) return;
+    uint32_t flags = G->flags;
+    if (G->phase != 3) {
+        // out of rounds (not expected): keep the FP64-verified upper end
+        flags |= FIF_IMF_UNRESOLVED;
+        G->m = G->ehi >= 0 ? G->ehi : A.max_inner;
+        G->sd_m = G->sd_hi;
+        G->sd_p = G->sd_lo;
+    }
+    S->L = G->L;
+    S->m = G->m;
+    S->sd = G->sd_m;
+    S->sd_prev = G->sd_p;
+    S->flags |= (int32_t)flags;
+    if (A.info) {
+        fif_imf_info* I = A.info + (int64_t)s * A.max_imfs + A.t;
+        I->k = S->k;
+        I->L = G->L;
+        I->m = G->m;
+        I->sd = G->sd_m;
+        I->sd_prev = G->sd_p;
+        I->flags = flags;
+        I->evals = (G->n32 & 0xffffu) | (G->n64 << 16);
+    }
+}
+
+// Run summaries, min and max of the FP64 residual written by k_pass2 for
+// signals whose row tiles are too thin for per-tile summaries.
+__global__ __launch_bounds__(kFftThreads) void k_count_resid(const SigDesc* __restrict__ sigs,
+                                                              const Work* __restrict__ work,
+                                                              const double* __restrict__ resid,
+                                                              RunState* __restrict__ parts,
+                                                              SigState* __restrict__ st)
+{
+    __shared__ RunState sh[kFftThreads / 64];
+    __shared__ double shd[2 * (kFftThreads / 64)];
+    const Work w = work[blockIdx.x];
+    const SigDesc d = sigs[w.sig];
+    if (!st[w.sig].active) return;
+    const int64_t t0 = (int64_t)w.tile * kFftCap;
+    const int64_t len = min((int64_t)kFftCap, d.N - t0);
+    const int chunk = (int)((len + kFftThreads - 1) / kFftThreads);
+    const int64_t a = (int64_t)threadIdx.x * chunk, b = min(len, a + chunk);
+    RunState r = run_empty();
+    double mn = INFINITY, mx = -INFINITY;
+    for (int64_t i = a; i < b; ++i) {
+        const double v = resid[d.resid_off + t0 + i];
+        run_push(r, v);
+        mn = fmin(mn, v);
+        mx = fmax(mx, v);
+    }
+    block_minmax<kFftThreads>(mn, mx, shd);
+    r = block_run_reduce<kFftThreads>(r, sh);
+    if (threadIdx.x == 0) {
+        parts[d.part_off + w.tile] = r;
+        atomicMin(&st[w.sig].kmin, dkey(mn));
+        atomicMax(&st[w.sig].kmax, dkey(mx));
+    }
+}
+
+}  // namespace fif

@@ -419,6 +419,7 @@ struct StepArgs {
     double2* spec1;
     double2* inter;
     RunState* parts;
+    double* resid;         // FP64 residuals of signals counted by k_count_resid
     int t;                 // outer step (MODE_STEP)
     int max_imfs;
 };
@@ -706,6 +707,16 @@ __global__ __launch_bounds__(kFftThreads) void k_pass2(StepArgs A, const InT* __
         const int cp = fdivmod(f, ftr, rl);
         row[(int64_t)N2 * cp + r0 + rl] = (OutT)lds[f].x;
     }
+    if (d.resid_off >= 0) {
+        // thin row tiles: hand the residual to k_count_resid
+        double* y = A.resid + d.resid_off;
+        for (int f = threadIdx.x; f < total; f += kFftThreads) {
+            int rl;
+            const int cp = fdivmod(f, ftr, rl);
+            y[(int64_t)N2 * cp + r0 + rl] = lds[f].y;
+        }
+        return;
+    }
     const int runs_per_row = N2 / TR;
     double mn = INFINITY, mx = -INFINITY;
     for (int cp = threadIdx.x; cp < N1; cp += kFftThreads) {
@@ -737,8 +748,9 @@ struct ScanArgs {
     const double* dtab;
     const double2* spec0;
     const double2* spec1;
-    float* gscr;              // per-signal FP32 scratch for N > register capacity
-    const int64_t* gscr_off;  // per-signal offset into gscr (floats), -1 if unused
+    float* gscr;              // FP32 scratch of the multi-workgroup scan (SigDesc::gs_off)
+    BigScan* bigs;            // multi-workgroup scan states (SigDesc::bs)
+    double* bpart;            // per-tile partial sums, 2*kBigCand per tile (SigDesc::bt_off)
     fif_imf_info* info;       // [B][max_imfs] or null
     int t;
     int max_imfs;
@@ -756,32 +768,17 @@ __device__ __forceinline__ int64_t mask_length(int64_t N, int64_t k, int rule, d
     return L < 1 ? 1 : L;
 }
 
-// Probes of the bracketing phase: m = 1, 2, 4, 16, ..., 4^10.
-constexpr int kGeo = 12;
-__device__ __forceinline__ int64_t geo_m(int q) { return q == 0 ? 1 : q == 1 ? 2 : ((int64_t)1 << (2 * (q - 1))); }
-
-// One workgroup per signal.  BPT > 0: thread-owned bins j = 1 + tid + i*T
-// (i < BPT) keep log2(mu) and the power in registers, power*lambda^2 in LDS;
-// BPT == 0: the same three FP32 values per bin live in global scratch.
-template <int BPT>
-__global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
+// Start of an outer step for one signal (whole workgroup): combine the run
+// summaries of the residual in sample order (extrema count; min/max come from
+// the atomics), apply the rounding floor and k < 2 stop rules, fix L and the
+// per-step power scale.  Leaves L (or -1 when the signal stops) in sh_i[0]
+// and the scale in sh_d[0] for every thread.
+template <int T>
+__device__ __forceinline__ void scan_prologue(const ScanArgs& A, int s, const SigDesc& d, SigState* S,
+                                              RunState* shr, int64_t* sh_i, double* sh_d)
 {
-    constexpr int T = kScanThreads;
-    constexpr int NR = BPT > 0 ? BPT : 1;
-    __shared__ RunState shr[T / 64];
-    __shared__ double shd[4 * (T / 64)];
-    __shared__ float shf[2 * kGeo * (T / 64)];
-    __shared__ int64_t sh_i[2];
-    __shared__ double sh_d[1];
-
-    const int s = A.list[blockIdx.x];
-    const SigDesc d = A.sigs[s];
-    SigState* S = A.st + s;
-    if (!S->active) return;
-    const LenPlan& lp = A.lens[d.len_id];
-    const int64_t N = d.N;
     const int tid = threadIdx.x;
-
+    const int64_t N = d.N;
     // ---- combine run summaries of the residual (sample order) ----
     {
         const int n = (A.t == 0) ? d.n_init_parts : d.n_parts;
@@ -835,6 +832,36 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
         }
         __syncthreads();
     }
+}
+
+// Probes of the bracketing phase: m = 1, 2, 4, 16, ..., 4^10.
+constexpr int kGeo = 12;
+__device__ __forceinline__ int64_t geo_m(int q) { return q == 0 ? 1 : q == 1 ? 2 : ((int64_t)1 << (2 * (q - 1))); }
+
+// One workgroup per signal with at most BPT * kScanThreads bins: thread-owned
+// bins j = 1 + tid + i*T (i < BPT) keep log2(mu) and the power in registers,
+// power*lambda^2 in LDS.
+template <int BPT>
+__global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
+{
+    constexpr int T = kScanThreads;
+    constexpr int NR = BPT;
+    __shared__ RunState shr[T / 64];
+    __shared__ double shd[4 * (T / 64)];
+    __shared__ float shf[2 * kGeo * (T / 64)];
+    __shared__ int64_t sh_i[2];
+    __shared__ double sh_d[1];
+
+    const int s = A.list[blockIdx.x];
+    const SigDesc d = A.sigs[s];
+    SigState* S = A.st + s;
+    if (!S->active) return;
+    const LenPlan& lp = A.lens[d.len_id];
+    const int64_t N = d.N;
+    const int tid = threadIdx.x;
+
+    // ---- combine run summaries, stop rules, mask length, power scale ----
+    scan_prologue<T>(A, s, d, S, shr, sh_i, sh_d);
     const int64_t L = sh_i[0];
     if (L < 0) return;
 
@@ -853,7 +880,6 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
     //      lambda_0 = 1 contributes to m = 1 only) ----
     float tau_r[NR], b_r[NR];
     extern __shared__ float lds_a[];
-    float* gs = (BPT == 0) ? (A.gscr + A.gscr_off[s]) : nullptr;
     auto weight = [&](int j) -> double { return (2 * (int64_t)j == N) ? 1.0 : 2.0; };
     auto sweep_bin = [&](int j, float& tau, float& av, float& bv) {
         const double2 v = R[j];
@@ -864,26 +890,16 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
         av = (float)(P * lam * lam);
         tau = 2.8853900817779268f * log1pf(-lf);  // 2 log2(1 - lambda)
     };
-    if (BPT > 0) {
 #pragma unroll
-        for (int i = 0; i < NR; ++i) {
-            const int j = 1 + tid + i * T;
-            float av = 0.f;
-            tau_r[i] = 0.f;
-            b_r[i] = 0.f;
-            if (j <= nh) sweep_bin(j, tau_r[i], av, b_r[i]);
-            lds_a[i * T + tid] = av;
-            // keep the FP64 work of different bins apart (register pressure)
-            __builtin_amdgcn_sched_barrier(0);
-        }
-    } else {
-        for (int j = 1 + tid; j <= nh; j += T) {
-            float tau, av, bv;
-            sweep_bin(j, tau, av, bv);
-            gs[3 * (j - 1)] = tau;
-            gs[3 * (j - 1) + 1] = av;
-            gs[3 * (j - 1) + 2] = bv;
-        }
+    for (int i = 0; i < NR; ++i) {
+        const int j = 1 + tid + i * T;
+        float av = 0.f;
+        tau_r[i] = 0.f;
+        b_r[i] = 0.f;
+        if (j <= nh) sweep_bin(j, tau_r[i], av, b_r[i]);
+        lds_a[i * T + tid] = av;
+        // keep the FP64 work of different bins apart (register pressure)
+        __builtin_amdgcn_sched_barrier(0);
     }
     const double P0 = (R[0].x * R[0].x + R[0].y * R[0].y) * pscale;
     __syncthreads();
@@ -901,24 +917,14 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
         float v[2] = {0.f, 0.f};
         const float e = (float)(m - 1);
         if (m == 1) {
-            if (BPT > 0) {
 #pragma unroll
-                for (int i = 0; i < NR; ++i) {
-                    v[0] += lds_a[i * T + tid];
-                    v[1] += b_r[i];
-                }
-            } else {
-                for (int j = 1 + tid; j <= nh; j += T) {
-                    v[0] += gs[3 * (j - 1) + 1];
-                    v[1] += gs[3 * (j - 1) + 2];
-                }
+            for (int i = 0; i < NR; ++i) {
+                v[0] += lds_a[i * T + tid];
+                v[1] += b_r[i];
             }
-        } else if (BPT > 0) {
+        } else {
 #pragma unroll
             for (int i = 0; i < NR; ++i) acc_bin(tau_r[i], lds_a[i * T + tid], b_r[i], e, v[0], v[1]);
-        } else {
-            for (int j = 1 + tid; j <= nh; j += T)
-                acc_bin(gs[3 * (j - 1)], gs[3 * (j - 1) + 1], gs[3 * (j - 1) + 2], e, v[0], v[1]);
         }
         if (m == 1 && tid == 0) {
             v[0] += (float)P0;

@@ -47,10 +47,34 @@ struct SigDesc {
     int64_t off;                   // element offset in packed signals/remainders
     int64_t spec_off;              // complex offset of its half spectrum (N/2+1 bins)
     int64_t inter_off;             // complex offset of its four-step intermediate
+    int64_t resid_off;             // offset of its FP64 residual buffer, -1 if unused
+    int64_t gs_off;                // offset (floats) of its multi-workgroup scan scratch
     int32_t len_id;
     int32_t part_off;              // offset of its run partials
     int32_t n_parts;               // run partials written per outer step
     int32_t n_init_parts;          // run partials written by the init statistics
+    int32_t bs;                    // multi-workgroup scan state index, -1 if not used
+    int32_t bt_off;                // first tile of its multi-workgroup scan partials
+    int32_t n_btiles;              // tiles of its multi-workgroup scan
+    int32_t pad;
+};
+
+// Multi-workgroup search for m (signals with more than one workgroup's bins).
+constexpr int kBigTile = 8192;     // bins per workgroup
+constexpr int kBigCand = 32;       // most candidates in one round (geometric probe, gallop)
+constexpr int kBigRefine = 7;      // candidates per round inside a bracket (octal search)
+constexpr int kBigRounds = 16;     // candidate rounds launched per outer step
+constexpr int kBigInactive = 4;    // phase of a signal that is not searching
+struct BigScan {
+    int64_t lo, hi;                // FP32 bracket: f(lo) > 0 (lo may be 0), f(hi) <= 0 (hi < 0: none yet)
+    int64_t elo, ehi;              // FP64 bracket, same convention
+    int64_t mt;                    // FP32 estimate
+    int64_t m, L;
+    double sd_lo, sd_hi, sd_m, sd_p, pscale;
+    int64_t cand[kBigCand];
+    int32_t phase;                 // 0 first round, 1 FP32 refine, 2 FP64, 3 done, 4 inactive
+    int32_t ncand;
+    uint32_t n32, n64, flags;
 };
 
 // Ordered summary of a run of consecutive samples: enough to count sign

@@ -92,7 +92,7 @@ def _signal(N, seed):
 
 
 @pytest.mark.parametrize("N", [2, 3, 8, 30, 105, 360, 1000, 2048, 4096, 6000, 8192,
-                               10000, 16384, 20736, 65536])
+                               10000, 16384, 20736, 65536, 131072, 196608])
 def test_fp64_single_matches_oracle(N):
     s = _signal(N, N)
     max_imfs = 6
@@ -228,6 +228,23 @@ def test_mask_rule_paper_constant(N):
     imfs = np.zeros((5, N))
     imfs[:res.n_imfs] = res.imfs.cpu().numpy()
     _check(ref, s, imfs, res.remainder.cpu().numpy(), res.info, res.n_imfs, 1e-3, True)
+
+
+def test_large_lengths_multi_workgroup_scan():
+    """Signals with more bins than one scan workgroup holds (N/2 > 32768)
+    mixed with small ones in one FP32 batch."""
+    lengths = [262144, 4096, 131072, 100000, 81920]
+    sigs = [_signal(N, 500 + i).astype(np.float32) for i, N in enumerate(lengths)]
+    plan, packed, out = _run_batch(lengths, sigs, 1e-3, 6, torch.float32)
+    info = out.info()
+    n = out.n_imfs.cpu().numpy()
+    assert np.all(info["flags"][:, :] & 4 == 0)  # never out of search rounds
+    print("  oracle for %d signals" % len(lengths), flush=True)
+    refs = oracle_many([s.astype(np.float64) for s in sigs], 1e-3, 6)
+    for b, ref in enumerate(refs):
+        s64 = sigs[b].astype(np.float64)
+        _check(ref, s64, out.imfs_of(b).cpu().numpy().astype(np.float64),
+               out.remainder_of(b).cpu().numpy().astype(np.float64), info[b], int(n[b]), 1e-3, False)
 
 
 def test_chirp_batch_full_size_sampled():
