@@ -182,6 +182,71 @@ typedef struct {
 fif_status fif_plan_profile(fif_plan* plan, int32_t enable);
 fif_status fif_plan_profile_read(fif_plan* plan, fif_kernel_time* out, int32_t cap, int32_t* n);
 
+/*
+ * Learned proposal of the inner step count (an addition to the paper's
+ * method).  A small network reads, for every outer step, the residual's
+ * power spectrum in 1024 contiguous bin groups and the mask length L, and
+ * proposes m; the Section 4 scan then starts from the proposal instead of
+ * its fixed geometric probes and still accepts only the count whose FP64
+ * stop test (equation "SD") gives SD_m <= delta < SD_{m-1}.  Decompositions
+ * with and without a proposal are therefore the same.
+ *
+ * Network: input rows [1024 positions][8 channels] of bfloat16 (channel 0:
+ * log2(mean group power / total power + 2^-60)/16 over groups of bins
+ * 1..N/2, channel 1: log2(L)/16, channels 2..7: 0); six convolutions of
+ * kernel 7, stride 2, zero padding 3, 64 channels and ReLU; mean over the
+ * last 16 positions; linear 64 -> 2 giving (log2(m)/16, log2(L)/16).  The
+ * FP32 parameter array (FIF_NET_PARAMS floats) holds, per layer l = 0..5,
+ * W_l[7][C_in][64] then bias_l[64] (C_in = 8 for l = 0, 64 after), then
+ * Wh[2][64], bh[2].  Convolutions run on bfloat16 operands with FP32
+ * accumulation; activations and backpropagated gradients are stored in
+ * bfloat16; the head, the loss and the Adam update are FP32.  Training loss:
+ * sum (y - target)^2 / (2 B).
+ *
+ * A model owns its device memory (parameters, Adam moments, activation and
+ * gradient buffers for up to max_batch rows), allocated on the current
+ * device by fif_model_create/fif_model_load.  Calls that take a stream are
+ * asynchronous; one model must not be used by two streams at once.
+ */
+#define FIF_NET_FEATURES 1024
+#define FIF_NET_CHANNELS 8
+#define FIF_NET_PARAMS 147458
+
+typedef struct fif_model fif_model;
+
+/* params: HOST [FIF_NET_PARAMS] (NULL: all zero).  max_batch >= 1. */
+fif_status fif_model_create(fif_model** model, const float* params, int32_t max_batch);
+fif_status fif_model_free(fif_model* model);
+/* Copy the FP32 parameters to / from HOST memory (set also clears the Adam
+   state).  Synchronous. */
+fif_status fif_model_get_params(const fif_model* model, float* params);
+fif_status fif_model_set_params(fif_model* model, const float* params);
+/* File: 8-byte magic "FIFNET01", int32 parameter count, int32 zero, then
+   the FP32 parameters (little endian). */
+fif_status fif_model_save(const fif_model* model, const char* path);
+fif_status fif_model_load(fif_model** model, const char* path, int32_t max_batch);
+/* feats: DEVICE bfloat16 bits [B][1024][8]; out: DEVICE FP32 [B][2];
+   1 <= B <= max_batch. */
+fif_status fif_model_forward(fif_model* model, const uint16_t* feats, int32_t B, float* out, void* stream);
+/* Loss and gradient without an update.  targets: DEVICE FP32 [B][2];
+   grad: DEVICE FP32 [FIF_NET_PARAMS] or NULL; loss: DEVICE FP32 [1] or NULL. */
+fif_status fif_model_grad(fif_model* model, const uint16_t* feats, const float* targets, int32_t B,
+                          float* grad, float* loss, void* stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias corrected) on the
+   gradient of one batch; loss (DEVICE FP32 [1]) may be NULL. */
+fif_status fif_model_train_step(fif_model* model, const uint16_t* feats, const float* targets, int32_t B,
+                                float lr, float* loss, void* stream);
+
+/* Use `model` (NULL: none) to propose m in every later decomposition with
+   this plan.  The model must live on the plan's device and outlive its use. */
+fif_status fif_plan_set_proposal(fif_plan* plan, fif_model* model);
+/* Record the network input rows of every outer step of later
+   decompositions with this plan: DEVICE bfloat16 bits
+   [B][max_imfs][1024][8] (row (b, j) = the residual that IMF j of signal b
+   came from; rows of steps that did not run are left as they were), or
+   NULL to stop recording. */
+fif_status fif_plan_record_features(fif_plan* plan, uint16_t* feats);
+
 #ifdef __cplusplus
 }
 #endif

@@ -18,11 +18,13 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from ._binding import (EXPORTED, IMF_CAP, IMF_INFO_DTYPE, IMF_REFINED, FifError, Options, check, load,
-                       LIB_PATH, STOP_FAILED, STOP_FEW_EXTREMA, STOP_FLOOR, STOP_MAX_IMFS)
+from ._binding import (EXPORTED, IMF_CAP, IMF_INFO_DTYPE, IMF_REFINED, NET_CHANNELS, NET_FEATURES, NET_PARAMS,
+                       FifError, Options, check, load, LIB_PATH, STOP_FAILED, STOP_FEW_EXTREMA, STOP_FLOOR,
+                       STOP_MAX_IMFS)
 
 __all__ = ["Options", "Plan", "BatchResult", "Decomposition", "decompose", "FifError", "IMF_CAP",
-           "IMF_REFINED", "IMF_INFO_DTYPE", "EXPORTED", "LIB_PATH", "load"]
+           "IMF_REFINED", "IMF_INFO_DTYPE", "EXPORTED", "LIB_PATH", "load", "Model", "NET_PARAMS",
+           "NET_FEATURES", "NET_CHANNELS"]
 
 
 def _torch():
@@ -114,6 +116,7 @@ class Plan:
         self.lengths = np.asarray(lengths, dtype=np.int64).ravel()
         self.offsets = np.concatenate([[0], np.cumsum(self.lengths)]).astype(np.int64)
         self.max_imfs = int(max_imfs)
+        self.B = len(self.lengths)
         self.total = int(self.offsets[-1])
         self._h = ctypes.c_void_p()
         arr = (ctypes.c_int64 * len(self.lengths))(*[int(v) for v in self.lengths])
@@ -152,6 +155,23 @@ class Plan:
             info_raw=torch.empty(B * self.max_imfs * IMF_INFO_DTYPE.itemsize, dtype=torch.uint8, device="cuda"),
             lengths=self.lengths, offsets=self.offsets, max_imfs=self.max_imfs)
 
+    def set_proposal(self, model: "Model | None") -> None:
+        """Let `model` propose m in later runs (None: plain search)."""
+        check(load().fif_plan_set_proposal(self._h, model._h if model is not None else None))
+        self._model = model      # keep it alive while the plan may use it
+
+    def record_features(self, feats) -> None:
+        """Record network inputs of later runs into `feats` (torch bfloat16,
+        [B * max_imfs, 1024, 8], row b * max_imfs + j), or stop (None)."""
+        torch = _torch()
+        if feats is not None:
+            shape = (self.B * self.max_imfs, NET_FEATURES, NET_CHANNELS)
+            if feats.dtype != torch.bfloat16 or tuple(feats.shape) != shape or not feats.is_cuda \
+                    or not feats.is_contiguous():
+                raise ValueError("feats must be a contiguous CUDA bfloat16 tensor of shape %s" % (shape,))
+        check(load().fif_plan_record_features(self._h, _ptr(feats) if feats is not None else None))
+        self._rec = feats
+
     def profile(self, enable: bool = True) -> None:
         """Bracket every later kernel launch of this plan with HIP events."""
         check(load().fif_plan_profile(self._h, 1 if enable else 0))
@@ -185,3 +205,88 @@ class Plan:
 
 def release_cache() -> None:
     load().fif_release_cache()
+
+
+class Model:
+    """Step-count proposal network (fif_model_*), parameters as FP32 numpy.
+
+    Inputs are torch bfloat16 CUDA tensors [B, 1024, 8]; targets FP32
+    [B, 2] = (log2(m)/16, log2(L)/16).
+    """
+
+    def __init__(self, params=None, max_batch: int = 256, path: str | None = None):
+        lib = load()
+        h = ctypes.c_void_p()
+        if path is not None:
+            check(lib.fif_model_load(ctypes.byref(h), path.encode(), int(max_batch)))
+        else:
+            arr = None
+            if params is not None:
+                p = np.ascontiguousarray(params, dtype=np.float32)
+                if p.size != NET_PARAMS:
+                    raise ValueError("expected %d parameters" % NET_PARAMS)
+                arr = p.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+            check(lib.fif_model_create(ctypes.byref(h), arr, int(max_batch)))
+        self._h = h.value
+        self.max_batch = int(max_batch)
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                load().fif_model_free(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(NET_PARAMS, dtype=np.float32)
+        check(load().fif_model_get_params(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return out
+
+    def set_params(self, params) -> None:
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != NET_PARAMS:
+            raise ValueError("expected %d parameters" % NET_PARAMS)
+        check(load().fif_model_set_params(self._h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+    def save(self, path: str) -> None:
+        check(load().fif_model_save(self._h, path.encode()))
+
+    def _check_feats(self, feats):
+        torch = _torch()
+        if feats.dtype != torch.bfloat16 or feats.dim() != 3 or tuple(feats.shape[1:]) != (NET_FEATURES, NET_CHANNELS) \
+                or not feats.is_cuda or not feats.is_contiguous():
+            raise ValueError("feats must be a contiguous CUDA bfloat16 tensor [B, %d, %d]" % (NET_FEATURES, NET_CHANNELS))
+        return int(feats.shape[0])
+
+    def forward(self, feats):
+        torch = _torch()
+        B = self._check_feats(feats)
+        out = torch.empty(B, 2, dtype=torch.float32, device=feats.device)
+        check(load().fif_model_forward(self._h, _ptr(feats), B, _ptr(out), _stream_ptr(torch)))
+        return out
+
+    def _targets(self, targets, B):
+        torch = _torch()
+        if targets.dtype != torch.float32 or tuple(targets.shape) != (B, 2) or not targets.is_cuda \
+                or not targets.is_contiguous():
+            raise ValueError("targets must be a contiguous CUDA float32 tensor [B, 2]")
+
+    def grad(self, feats, targets):
+        """(loss, gradient) of one batch, both torch FP32 CUDA tensors."""
+        torch = _torch()
+        B = self._check_feats(feats)
+        self._targets(targets, B)
+        g = torch.empty(NET_PARAMS, dtype=torch.float32, device=feats.device)
+        loss = torch.empty(1, dtype=torch.float32, device=feats.device)
+        check(load().fif_model_grad(self._h, _ptr(feats), _ptr(targets), B, _ptr(g), _ptr(loss),
+                                    _stream_ptr(torch)))
+        return loss, g
+
+    def train_step(self, feats, targets, lr: float, loss=None):
+        """One Adam step; writes the batch loss into `loss` (FP32 [1]) if given."""
+        torch = _torch()
+        B = self._check_feats(feats)
+        self._targets(targets, B)
+        check(load().fif_model_train_step(self._h, _ptr(feats), _ptr(targets), B, float(lr), _ptr(loss),
+                                          _stream_ptr(torch)))

@@ -35,7 +35,14 @@ EXPORTED = (
     "fif_decompose_batched", "fif_decompose_batched_f64",
     "fif_decompose", "fif_decompose_f64", "fif_release_cache",
     "fif_plan_profile", "fif_plan_profile_read",
+    "fif_model_create", "fif_model_free", "fif_model_get_params", "fif_model_set_params",
+    "fif_model_save", "fif_model_load", "fif_model_forward", "fif_model_grad", "fif_model_train_step",
+    "fif_plan_set_proposal", "fif_plan_record_features",
 )
+
+NET_FEATURES = 1024
+NET_CHANNELS = 8
+NET_PARAMS = 147458
 
 
 class FifError(RuntimeError):
@@ -107,6 +114,29 @@ def load():
     lib.fif_plan_profile.argtypes = [vp, i32]
     lib.fif_plan_profile_read.restype = ctypes.c_int
     lib.fif_plan_profile_read.argtypes = [vp, ctypes.POINTER(KernelTime), i32, ctypes.POINTER(i32)]
+    fp = ctypes.POINTER(ctypes.c_float)
+    lib.fif_model_create.restype = ctypes.c_int
+    lib.fif_model_create.argtypes = [ctypes.POINTER(vp), fp, i32]
+    lib.fif_model_free.restype = ctypes.c_int
+    lib.fif_model_free.argtypes = [vp]
+    lib.fif_model_get_params.restype = ctypes.c_int
+    lib.fif_model_get_params.argtypes = [vp, fp]
+    lib.fif_model_set_params.restype = ctypes.c_int
+    lib.fif_model_set_params.argtypes = [vp, fp]
+    lib.fif_model_save.restype = ctypes.c_int
+    lib.fif_model_save.argtypes = [vp, ctypes.c_char_p]
+    lib.fif_model_load.restype = ctypes.c_int
+    lib.fif_model_load.argtypes = [ctypes.POINTER(vp), ctypes.c_char_p, i32]
+    lib.fif_model_forward.restype = ctypes.c_int
+    lib.fif_model_forward.argtypes = [vp, vp, i32, vp, vp]
+    lib.fif_model_grad.restype = ctypes.c_int
+    lib.fif_model_grad.argtypes = [vp, vp, vp, i32, vp, vp, vp]
+    lib.fif_model_train_step.restype = ctypes.c_int
+    lib.fif_model_train_step.argtypes = [vp, vp, vp, i32, ctypes.c_float, vp, vp]
+    lib.fif_plan_set_proposal.restype = ctypes.c_int
+    lib.fif_plan_set_proposal.argtypes = [vp, vp]
+    lib.fif_plan_record_features.restype = ctypes.c_int
+    lib.fif_plan_record_features.argtypes = [vp, vp]
     _lib = lib
     return lib
 

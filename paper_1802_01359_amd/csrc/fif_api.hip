@@ -17,6 +17,8 @@
 
 #include "../../include/fif.h"
 #include "fif_bigscan.hpp"
+#include "fif_model_internal.hpp"
+#include "fif_propose.hpp"
 
 using namespace fif;
 
@@ -86,6 +88,10 @@ struct DevBuf {
 
 }  // namespace
 
+namespace fif {
+fif_status fif_internal_fail(fif_status st, const std::string& msg) { return fail(st, "%s", msg.c_str()); }
+}  // namespace fif
+
 struct fif_plan {
     int device = 0;
     int32_t B = 0, max_imfs = 0;
@@ -115,7 +121,10 @@ struct fif_plan {
     double2* d_ctab = nullptr;
     // workspace layout (byte offsets)
     size_t ws_state = 0, ws_spec0 = 0, ws_spec1 = 0, ws_inter = 0, ws_parts = 0, ws_psum = 0, ws_gscr = 0,
-           ws_bigs = 0, ws_bpart = 0, ws_resid = 0, ws_total = 0;
+           ws_bigs = 0, ws_bpart = 0, ws_resid = 0, ws_feat = 0, ws_prop = 0, ws_total = 0;
+    // learned proposal of m, and recording of the network inputs
+    fif_model* model = nullptr;
+    uint16_t* rec = nullptr;
     // kernel timing (fif_plan_profile)
     struct Rec {
         int kind;
@@ -165,7 +174,8 @@ fif_status set_lds_limits()
         set((const void*)k_pass2<MODE_FORWARD, double, double>);
         set((const void*)k_pass2<MODE_STEP, double, double>);
         set((const void*)k_pass2<MODE_REMAINDER, double, double>);
-        set((const void*)k_scan<kScanBinsPerThread>);
+        set((const void*)k_scan<kScanBinsPerThread, false>);
+        set((const void*)k_scan<kScanBinsPerThread, true>);
     });
     if (err != hipSuccess) return fail(FIF_ERR_DEVICE, "hipFuncSetAttribute: %s", hipGetErrorString(err));
     return FIF_OK;
@@ -446,6 +456,10 @@ fif_status fif_plan_create(fif_plan** out, const int64_t* lengths, int32_t B, in
     ws += sizeof(double) * 2 * kBigCand * (size_t)btiles;
     p->ws_resid = ws = align_up(ws, 256);
     ws += sizeof(double) * (size_t)resid;
+    p->ws_feat = ws = align_up(ws, 256);
+    ws += sizeof(uint16_t) * (size_t)kNetFeat * kNetCin0 * (size_t)B;
+    p->ws_prop = ws = align_up(ws, 256);
+    ws += sizeof(int64_t) * (size_t)B;
     p->ws_total = align_up(ws, 256);
 
     // metadata upload
@@ -607,6 +621,7 @@ Bound bind(const fif_plan* p, void* ws, double delta, fif_imf_info* info)
     S.bigs = (BigScan*)(w + p->ws_bigs);
     S.bpart = (double*)(w + p->ws_bpart);
     S.info = info;
+    S.prop = nullptr;
     S.t = 0;
     S.max_imfs = p->max_imfs;
     S.delta = delta;
@@ -648,22 +663,78 @@ void launch_init(const fif_plan* p, Bound& b, const T* x, hipStream_t s)
     }
 }
 
-template <typename T>
-void launch_step(const fif_plan* p, Bound& b, int t, const T* x, T* imfs, hipStream_t s)
+// Search for m of every active signal.  With a proposal model or feature
+// recording the step starts (count combine, stop rules, L) run first, then
+// the features, the network and the proposals, then the searches.
+void launch_scan(const fif_plan* p, Bound& b, int t, void* ws, hipStream_t s)
 {
     ScanArgs S = b.sc;
     S.t = t;
-    if (!p->scan_small.empty()) {
-        S.list = p->d_scan_small;
-        Timed tm(p, "scan", s);
-        k_scan<kScanBinsPerThread><<<(unsigned)p->scan_small.size(), kScanThreads,
-                                     sizeof(float) * kScanBinsPerThread * kScanThreads, s>>>(S);
+    const bool split = p->model || p->rec;
+    const unsigned nb = (unsigned)p->scan_big.size(), nt = (unsigned)p->w_btile.size();
+    const size_t scan_lds = sizeof(float) * kScanBinsPerThread * kScanThreads;
+    if (!split) {
+        if (!p->scan_small.empty()) {
+            S.list = p->d_scan_small;
+            Timed tm(p, "scan", s);
+            k_scan<kScanBinsPerThread, false><<<(unsigned)p->scan_small.size(), kScanThreads, scan_lds, s>>>(S);
+        }
+        if (nb) {
+            Timed tm(p, "scan_big", s);
+            S.list = p->d_scan_big;
+            k_bscan_prep<kScanThreads><<<nb, kScanThreads, 0, s>>>(S);
+        }
+    } else {
+        {
+            Timed tm(p, "scan_prologue", s);
+            if (!p->scan_small.empty()) {
+                S.list = p->d_scan_small;
+                k_scan_prologue<kScanThreads><<<(unsigned)p->scan_small.size(), kScanThreads, 0, s>>>(S);
+            }
+            if (nb) {
+                S.list = p->d_scan_big;
+                k_bscan_prep<kScanThreads><<<nb, kScanThreads, 0, s>>>(S);
+            }
+        }
+        char* w = (char*)ws;
+        uint16_t* feat = (uint16_t*)(w + p->ws_feat);
+        int64_t* prop = (int64_t*)(w + p->ws_prop);
+        {
+            Timed tm(p, "features", s);
+            FeatArgs F;
+            F.sigs = p->d_sigs;
+            F.st = S.st;
+            F.spec0 = S.spec0;
+            F.spec1 = S.spec1;
+            F.t = t;
+            F.out = feat;
+            F.rec = p->rec;
+            F.max_imfs = p->max_imfs;
+            k_features<<<(unsigned)p->B, kNetThreads, 0, s>>>(F);
+        }
+        if (p->model) {
+            Timed tm(p, "propose", s);
+            const int mb = model_max_batch(p->model);
+            for (int s0 = 0; s0 < p->B; s0 += mb) {
+                const int n = std::min(mb, p->B - s0);
+                const float* y = model_infer(p->model, feat + (size_t)s0 * kNetFeat * kNetCin0, n, s);
+                k_propose<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(y, s0, n, p->opt.max_inner, S.st, prop);
+            }
+            S.prop = prop;
+        }
+        if (!p->scan_small.empty()) {
+            S.list = p->d_scan_small;
+            Timed tm(p, "scan", s);
+            k_scan<kScanBinsPerThread, true><<<(unsigned)p->scan_small.size(), kScanThreads, scan_lds, s>>>(S);
+        }
+        if (nb && p->model) {
+            S.list = p->d_scan_big;
+            k_bscan_seed<<<nb, 64, 0, s>>>(S);
+        }
     }
-    if (!p->scan_big.empty()) {
+    if (nb) {
         Timed tm(p, "scan_big", s);
         S.list = p->d_scan_big;
-        const unsigned nb = (unsigned)p->scan_big.size(), nt = (unsigned)p->w_btile.size();
-        k_bscan_prep<kScanThreads><<<nb, kScanThreads, 0, s>>>(S);
         k_bscan_round<kScanThreads, true><<<nt, kScanThreads, 0, s>>>(S, p->d_btile);
         k_bscan_decide<<<nb, 64 * kDecideGroups, 0, s>>>(S);
         for (int r = 0; r < kBigRounds; ++r) {
@@ -672,6 +743,12 @@ void launch_step(const fif_plan* p, Bound& b, int t, const T* x, T* imfs, hipStr
         }
         k_bscan_final<kScanThreads><<<nb, 64, 0, s>>>(S);
     }
+}
+
+template <typename T>
+void launch_step(const fif_plan* p, Bound& b, int t, const T* x, T* imfs, void* ws, hipStream_t s)
+{
+    launch_scan(p, b, t, ws, s);
     StepArgs A = b.sa;
     A.t = t;
     if (!p->w_single.empty()) {
@@ -738,7 +815,7 @@ fif_status batched(fif_plan* p, const T* x, double delta, T* imfs, T* rem, int32
     hipStream_t s = (hipStream_t)stream;
     Bound b = bind(p, ws, delta, info);
     launch_init<T>(p, b, x, s);
-    for (int t = 0; t < p->max_imfs; ++t) launch_step<T>(p, b, t, x, imfs, s);
+    for (int t = 0; t < p->max_imfs; ++t) launch_step<T>(p, b, t, x, imfs, ws, s);
     launch_final<T>(p, b, x, rem, n_imfs, sig_status, info, s);
     HIP_TRY(hipGetLastError());
     return FIF_OK;
@@ -814,7 +891,7 @@ fif_status single(const T* x, int64_t N, fif_window window, double delta, int32_
     Bound b = bind(p, it->second.ws, delta, info);
     launch_init<T>(p, b, x, s);
     for (int t = 0; t < max_imfs; ++t) {
-        launch_step<T>(p, b, t, x, imfs, s);
+        launch_step<T>(p, b, t, x, imfs, it->second.ws, s);
         HIP_TRY(hipMemcpyAsync(hs, b.state, sizeof(SigState), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         if (!hs->active) {
@@ -862,6 +939,25 @@ fif_status fif_decompose_f64(const double* signal, int64_t N, fif_window window,
                              const fif_options* opt, void* stream)
 {
     return single<double>(signal, N, window, delta, max_imfs, imfs, remainder, n_imfs, info, opt, stream);
+}
+
+fif_status fif_plan_set_proposal(fif_plan* plan, fif_model* model)
+{
+    g_err.clear();
+    if (!plan) return fail(FIF_ERR_INVALID_ARG, "plan is null");
+    if (model && model_device(model) != plan->device)
+        return fail(FIF_ERR_INVALID_ARG, "model and plan live on different devices");
+    plan->model = model;
+    return FIF_OK;
+}
+
+fif_status fif_plan_record_features(fif_plan* plan, uint16_t* feats)
+{
+    g_err.clear();
+    if (!plan) return fail(FIF_ERR_INVALID_ARG, "plan is null");
+    if (((uintptr_t)feats) % 16) return fail(FIF_ERR_INVALID_ARG, "feats must be 16-byte aligned");
+    plan->rec = feats;
+    return FIF_OK;
 }
 
 fif_status fif_plan_profile(fif_plan* plan, int32_t enable)

@@ -73,6 +73,7 @@ __global__ __launch_bounds__(T) void k_bscan_prep(ScanArgs A)
         if (L < 0) {
             G->phase = kBigInactive;
         } else {
+            S->L = L;
             G->phase = 0;
             G->L = L;
             G->pscale = sh_d[0];
@@ -91,6 +92,30 @@ __global__ __launch_bounds__(T) void k_bscan_prep(ScanArgs A)
             G->ncand = n;
         }
     }
+}
+
+// First-round candidates around a proposed m (one workgroup of 64 threads
+// per signal, thread 0 works): m_p * 2^((i - 10)/8), i = 0..20, rounded,
+// clamped to [1, cap] and made strictly increasing.  Signals without a
+// proposal keep the geometric probes of k_bscan_prep.
+__global__ void k_bscan_seed(ScanArgs A)
+{
+    if (threadIdx.x != 0) return;
+    const int s = A.list[blockIdx.x];
+    const SigDesc d = A.sigs[s];
+    BigScan* G = A.bigs + d.bs;
+    if (G->phase != 0 || !A.prop) return;
+    const int64_t mp = A.prop[s];
+    if (mp <= 0) return;
+    const int64_t cap = A.max_inner;
+    int n = 0;
+    for (int i = 0; i <= 20 && n < kBigCand; ++i) {
+        int64_t c = (int64_t)llrint((double)mp * exp2((double)(i - 10) / 8.0));
+        c = max((int64_t)1, min(cap, c));
+        if (n > 0 && c <= G->cand[n - 1]) continue;
+        G->cand[n++] = c;
+    }
+    G->ncand = n;
 }
 
 // Partial sums of the current candidates over this tile's bins, left in

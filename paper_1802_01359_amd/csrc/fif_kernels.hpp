@@ -752,6 +752,7 @@ struct ScanArgs {
     BigScan* bigs;            // multi-workgroup scan states (SigDesc::bs)
     double* bpart;            // per-tile partial sums, 2*kBigCand per tile (SigDesc::bt_off)
     fif_imf_info* info;       // [B][max_imfs] or null
+    const int64_t* prop;      // proposed m per signal (0: none), or null
     int t;
     int max_imfs;
     double delta;
@@ -834,14 +835,31 @@ __device__ __forceinline__ void scan_prologue(const ScanArgs& A, int s, const Si
     }
 }
 
+// The start of an outer step alone, for the proposal path: the network needs
+// L before the search for m starts.
+template <int T>
+__global__ __launch_bounds__(T) void k_scan_prologue(ScanArgs A)
+{
+    __shared__ RunState shr[T / 64];
+    __shared__ int64_t sh_i[2];
+    __shared__ double sh_d[1];
+    const int s = A.list[blockIdx.x];
+    const SigDesc d = A.sigs[s];
+    SigState* S = A.st + s;
+    if (!S->active) return;
+    scan_prologue<T>(A, s, d, S, shr, sh_i, sh_d);
+    if (threadIdx.x == 0 && sh_i[0] >= 0) S->L = sh_i[0];
+}
+
 // Probes of the bracketing phase: m = 1, 2, 4, 16, ..., 4^10.
 constexpr int kGeo = 12;
 __device__ __forceinline__ int64_t geo_m(int q) { return q == 0 ? 1 : q == 1 ? 2 : ((int64_t)1 << (2 * (q - 1))); }
 
 // One workgroup per signal with at most BPT * kScanThreads bins: thread-owned
 // bins j = 1 + tid + i*T (i < BPT) keep log2(mu) and the power in registers,
-// power*lambda^2 in LDS.
-template <int BPT>
+// power*lambda^2 in LDS.  PRE: k_scan_prologue already ran (L and the power
+// scale are in the signal state).
+template <int BPT, bool PRE>
 __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
 {
     constexpr int T = kScanThreads;
@@ -861,7 +879,13 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
     const int tid = threadIdx.x;
 
     // ---- combine run summaries, stop rules, mask length, power scale ----
-    scan_prologue<T>(A, s, d, S, shr, sh_i, sh_d);
+    if (!PRE) {
+        scan_prologue<T>(A, s, d, S, shr, sh_i, sh_d);
+    } else if (tid == 0) {
+        sh_i[0] = S->L;
+        sh_d[0] = S->pscale;
+    }
+    if (PRE) __syncthreads();
     const int64_t L = sh_i[0];
     if (L < 0) return;
 
@@ -943,26 +967,66 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
     {
         int64_t lo = 0, hi = -1;
         float flo = INFINITY, fhi = 0.f;
-        for (int q = 0; q < kGeo; ++q) {
-            const int64_t mq = geo_m(q);
-            if (mq >= cap) break;
-            const float fq = f32(mq);
-            if (fq <= 0.f) {
-                hi = mq;
-                fhi = fq;
-                break;
-            }
-            lo = mq;
-            flo = fq;
-        }
-        if (hi < 0) {
-            // no probe below the cap satisfies the test
-            const float fc = f32(cap);
+        const int64_t mp = A.prop ? A.prop[s] : 0;
+        if (mp > 0) {
+            // bracket from the proposal: probe it, then walk away from it
+            // in steps growing fourfold from mp/16 until f changes sign
+            int64_t c = min(mp, cap);
+            int64_t step = max((int64_t)1, c >> 4);
+            float fc = f32(c);
             if (fc <= 0.f) {
-                hi = cap;
+                hi = c;
                 fhi = fc;
+                while (hi > 1) {
+                    c = max((int64_t)1, hi - step);
+                    fc = f32(c);
+                    if (fc > 0.f) {
+                        lo = c;
+                        flo = fc;
+                        break;
+                    }
+                    hi = c;
+                    fhi = fc;
+                    step *= 4;
+                }
             } else {
-                lo = cap;
+                lo = c;
+                flo = fc;
+                while (lo < cap) {
+                    c = min(cap, lo + step);
+                    fc = f32(c);
+                    if (fc <= 0.f) {
+                        hi = c;
+                        fhi = fc;
+                        break;
+                    }
+                    lo = c;
+                    flo = fc;
+                    step *= 4;
+                }
+            }
+        } else {
+            for (int q = 0; q < kGeo; ++q) {
+                const int64_t mq = geo_m(q);
+                if (mq >= cap) break;
+                const float fq = f32(mq);
+                if (fq <= 0.f) {
+                    hi = mq;
+                    fhi = fq;
+                    break;
+                }
+                lo = mq;
+                flo = fq;
+            }
+            if (hi < 0) {
+                // no probe below the cap satisfies the test
+                const float fc = f32(cap);
+                if (fc <= 0.f) {
+                    hi = cap;
+                    fhi = fc;
+                } else {
+                    lo = cap;
+                }
             }
         }
         if (hi < 0) {
