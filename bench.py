@@ -16,6 +16,11 @@ Workloads (synthetic, seeded; see siggen):
   tones3  one FP64 signal, N = 4096, three AM tones, delta 1e-3, 8 IMFs
   plain   the chirps batch through the plain single-signal entry point
           (one signal at a time, host loop per outer step)
+  learned 4096 FP32 signals, N = 65536, three AM tones at log-uniform
+          frequencies + N(0, 0.01^2) noise (held-out members of the family the
+          proposal network was trained on), delta 1e-3, 8 IMFs, with the
+          trained network proposing m; the same batch without proposals is
+          timed after it and reported beside
 """
 from __future__ import annotations
 
@@ -34,6 +39,7 @@ sys.path.insert(0, ROOT)
 METRIC = "signal samples decomposed/sec (FP32 batched FIF) vs plain, % HBM peak"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+MODEL_FILE = os.path.join(ROOT, "paper_1802_01359_amd", "data", "proposal_tones3_65536.fifnet")
 
 
 def log(*a):
@@ -53,6 +59,10 @@ def workload(name: str):
     if name == "long":
         return dict(workload="long-1x16777216", lengths=[1 << 24], delta=1e-3, max_imfs=20, io="f32",
                     make=lambda: [siggen.long_drift()])
+    if name == "learned":
+        B, N, first = 4096, 65536, 10_000_000
+        return dict(workload="learned-4096x65536", lengths=[N] * B, delta=1e-3, max_imfs=8, io="f32",
+                    make=lambda: [siggen.train_signal(first + i, N) for i in range(B)])
     if name == "tones3":
         return dict(workload="tones3-1x4096", lengths=[4096], delta=1e-3, max_imfs=8, io="f64",
                     make=lambda: [siggen.tones3()])
@@ -130,7 +140,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="chirps", choices=["chirps", "uneven", "long", "tones3", "plain"])
+    ap.add_argument("--workload", default="chirps", choices=["chirps", "uneven", "long", "tones3", "plain", "learned"])
+    ap.add_argument("--model", default=MODEL_FILE, help="proposal network file (learned workload)")
     ap.add_argument("--cpu-signals", type=int, default=2, help="signals the CPU oracle decomposes")
     ap.add_argument("--cpu-budget", type=float, default=25.0, help="seconds of CPU oracle work at most")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -167,6 +178,7 @@ def main():
     delta = W["delta"]
 
     roofline = None
+    extra = {}
     if args.workload == "plain":
         # plain single-signal form, one signal after another, host loop per outer step
         N = lengths[0]
@@ -187,6 +199,10 @@ def main():
     else:
         plan = fif.Plan(lengths, J)
         out = plan.alloc_outputs(dt)
+        model = None
+        if args.workload == "learned":
+            model = fif.Model(path=args.model, max_batch=1024)
+            plan.set_proposal(model)
         for _ in range(args.warmup):
             plan.run(packed, delta, out=out)
         torch.cuda.synchronize()
@@ -200,6 +216,29 @@ def main():
         el = time.perf_counter() - t0
         prof = plan.profile_read()
         plan.profile(False)
+        extra = {}
+        if model is not None:
+            # the same batch with the plain search, for comparison
+            ref_info = out.info()
+            plan.set_proposal(None)
+            ref = plan.alloc_outputs(dt)
+            plan.run(packed, delta, out=ref)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(args.steps):
+                plan.run(packed, delta, out=ref)
+            torch.cuda.synchronize()
+            el_plain = time.perf_counter() - t1
+            pinf = ref.info()
+            same = bool(np.array_equal(pinf["m"], ref_info["m"]) and np.array_equal(pinf["L"], ref_info["L"])
+                        and torch.equal(ref.imfs, out.imfs))
+            pm = np.arange(J)[None, :] < ref.n_imfs.cpu().numpy()[:, None]
+            extra = {"plain_search_ms_per_step": 1e3 * el_plain / args.steps,
+                     "plain_search_value": total * args.steps / el_plain,
+                     "plain_fp32_passes_per_imf": float((pinf["evals"][pm] & 0xffff).mean()),
+                     "identical_to_plain": same}
+            log("plain search: %.2f ms/step, FP32 passes per IMF %.2f, identical %s" % (
+                extra["plain_search_ms_per_step"], extra["plain_fp32_passes_per_imf"], same))
         n_imfs = out.n_imfs.cpu().numpy()
         st = out.sig_status.cpu().numpy()
         assert np.all(st == 0), "non-finite synthetic input"
@@ -246,8 +285,11 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": W["workload"], "signals": len(lengths), "samples": total, "delta": delta,
                    "max_imfs": J, "io_dtype": W["io"],
-                   "form": "plain single-signal" if args.workload == "plain" else "batched"},
+                   "form": "plain single-signal" if args.workload == "plain" else
+                   ("batched, learned proposal of m" if args.workload == "learned" else "batched")},
     }
+    if args.workload not in ("plain",) and extra:
+        res["config"].update(extra)
     if roofline is not None:
         res["roofline"] = roofline
     if not args.no_cpu_baseline:

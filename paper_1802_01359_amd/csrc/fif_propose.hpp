@@ -23,33 +23,59 @@ struct FeatArgs {
     int max_imfs;
 };
 
+// Bins are read once, coalesced, in tiles of kFeatTile staged in LDS; each
+// group's sum accumulates (in bin order) in an LDS slot owned by one thread
+// per tile, and the total is an ordered block sum of the per-thread tile
+// sums.
+constexpr int kFeatTile = 2048;
+
+__device__ __forceinline__ int64_t feat_j0(int q, int64_t H) { return ((int64_t)q * H) / kNetFeat; }
+__device__ __forceinline__ int64_t feat_j1(int q, int64_t H)
+{
+    return max(((int64_t)(q + 1) * H) / kNetFeat, feat_j0(q, H) + 1);
+}
+
 __global__ __launch_bounds__(kNetThreads) void k_features(FeatArgs A)
 {
+    __shared__ double pw[kFeatTile];
+    __shared__ double gs[kNetFeat];
     __shared__ double shd[kNetThreads / 64];
     const int s = blockIdx.x;
     const SigState* S = A.st + s;
     if (!S->active) return;
     const SigDesc d = A.sigs[s];
-    const double2* R = ((A.t & 1) ? A.spec1 : A.spec0) + d.spec_off;
+    const double2* R = ((A.t & 1) ? A.spec1 : A.spec0) + d.spec_off + 1;   // R[u] = bin u + 1
     const int64_t H = d.N / 2;
+    const int tid = threadIdx.x;
+    for (int q = tid; q < kNetFeat; q += kNetThreads) gs[q] = 0.0;
     double tot[1] = {0.0};
-    for (int64_t j = 1 + threadIdx.x; j <= H; j += kNetThreads) {
-        const double2 z = R[j];
-        tot[0] += z.x * z.x + z.y * z.y;
+    for (int64_t t0 = 0; t0 < H; t0 += kFeatTile) {
+        const int n = (int)min((int64_t)kFeatTile, H - t0);
+        __syncthreads();
+        for (int i = tid; i < n; i += kNetThreads) {
+            const double2 z = R[t0 + i];
+            const double v = z.x * z.x + z.y * z.y;
+            pw[i] = v;
+            tot[0] += v;
+        }
+        __syncthreads();
+        // groups meeting [t0, t0 + n): each summed by one thread, in bin order
+        const int qa = (int)max((int64_t)0, (t0 * kNetFeat) / H - 1);
+        const int qb = (int)min((int64_t)kNetFeat - 1, ((t0 + n) * kNetFeat) / H + 1);
+        for (int q = qa + tid; q <= qb; q += kNetThreads) {
+            const int64_t a = max(feat_j0(q, H), t0), b = min(feat_j1(q, H), t0 + n);
+            double acc = 0.0;
+            for (int64_t u = a; u < b; ++u) acc += pw[u - t0];
+            if (b > a) gs[q] += acc;
+        }
     }
     block_sum<double, kNetThreads, 1>(tot, shd);
     const float lch = (float)(log2((double)S->L) / 16.0);
     bf16* o0 = (bf16*)A.out + (int64_t)s * kNetFeat * kNetCin0;
     bf16* o1 = A.rec ? (bf16*)A.rec + ((int64_t)s * A.max_imfs + A.t) * kNetFeat * kNetCin0 : nullptr;
-    for (int q = threadIdx.x; q < kNetFeat; q += kNetThreads) {
-        const int64_t j0 = ((int64_t)q * H) / kNetFeat;
-        const int64_t j1 = max(((int64_t)(q + 1) * H) / kNetFeat, j0 + 1);
-        double sum = 0.0;
-        for (int64_t j = j0; j < j1; ++j) {
-            const double2 z = R[1 + j];
-            sum += z.x * z.x + z.y * z.y;
-        }
-        const double v = tot[0] > 0.0 ? log2(sum / (double)(j1 - j0) / tot[0] + 0x1p-60) / 16.0 : -60.0 / 16.0;
+    for (int q = tid; q < kNetFeat; q += kNetThreads) {
+        const double cnt = (double)(feat_j1(q, H) - feat_j0(q, H));
+        const double v = tot[0] > 0.0 ? log2(gs[q] / cnt / tot[0] + 0x1p-60) / 16.0 : -60.0 / 16.0;
         bf16x8 row = bf16x8_zero();
         row[0] = (bf16)(float)v;
         row[1] = (bf16)lch;

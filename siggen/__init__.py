@@ -157,3 +157,35 @@ def train_signal(index: int, N: int = 65536) -> np.ndarray:
         a = 1.0 + 0.3 * sg * np.sin(2 * np.pi * x)
         s += a * np.cos(2 * np.pi * f * x + rng.uniform(0, 2 * np.pi))
     return s + 0.01 * rng.standard_normal(N)
+
+
+def train_params(index: int, N: int = 65536) -> np.ndarray:
+    """(frequency, AM sign, phase) of the three tones of train_signal(index)."""
+    rng = rng_for(W_TRAIN, index)
+    out = np.empty((3, 3))
+    for c in range(3):
+        out[c, 0] = math.exp(rng.uniform(math.log(4.0), math.log(N / 8.0)))
+        out[c, 1] = 1.0 if rng.uniform() < 0.5 else -1.0
+        out[c, 2] = rng.uniform(0, 2 * np.pi)
+    return out
+
+
+def train_batch(first: int, count: int, N: int = 65536, device: str = "cuda"):
+    """Signals first .. first+count-1 of the train_signal family synthesised on
+    the device (torch, FP64 then rounded to FP32): the same tones as
+    train_signal, with N(0, 0.01^2) noise from a torch generator seeded with
+    (W_TRAIN, first) instead of numpy's stream.  Returns [count, N] FP32."""
+    import torch
+    P = torch.tensor(np.stack([train_params(first + i, N) for i in range(count)]), dtype=torch.float64,
+                     device=device)                                   # [count, 3, 3]
+    x = torch.arange(N, dtype=torch.float64, device=device) / N
+    two_pi = 2.0 * math.pi
+    am = torch.sin(two_pi * x)                                        # [N]
+    s = torch.zeros(count, N, dtype=torch.float64, device=device)
+    for c in range(3):
+        f, sg, ph = P[:, c, 0:1], P[:, c, 1:2], P[:, c, 2:3]
+        s += (1.0 + 0.3 * sg * am) * torch.cos(two_pi * f * x + ph)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(np.random.SeedSequence([W_TRAIN, int(first)]).generate_state(1)[0]))
+    s += 0.01 * torch.randn(count, N, dtype=torch.float64, device=device, generator=g)
+    return s.to(torch.float32)

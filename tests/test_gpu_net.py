@@ -8,6 +8,8 @@ plain one (decisions and IMFs bitwise identical, whatever the proposals).
 """
 from __future__ import annotations
 
+import os
+
 import numpy as np
 import pytest
 
@@ -163,3 +165,19 @@ def test_proposal_keeps_the_decomposition(proposal):
     assert torch.equal(out.imfs, ref_imfs)
     assert torch.equal(out.remainders, ref_rem)
     plan.set_proposal(None)
+
+
+def test_trained_network_gains_and_keeps_the_decomposition():
+    """The committed network (trained on the GPU by
+    `python -m paper_1802_01359_amd.proposal train`) on held-out signals:
+    same decomposition, fewer FP32 passes of the search per IMF."""
+    from paper_1802_01359_amd import proposal
+    path = os.path.join(os.path.dirname(fif.__file__), "data", "proposal_tones3_65536.fifnet")
+    model = fif.Model(path=path, max_batch=256)
+    print("trained proposal on 256 held-out signals", flush=True)
+    r = proposal.evaluate(model, count=256, repeats=1)
+    print(r, flush=True)
+    assert r["identical"]
+    assert r["proposal"]["imfs"] == r["plain"]["imfs"]
+    assert r["proposal"]["fp32_passes_per_imf"] <= 0.7 * r["plain"]["fp32_passes_per_imf"]
+    assert r["log2_m_abs_err_mean"] < 0.6
