@@ -201,7 +201,7 @@ def main():
         out = plan.alloc_outputs(dt)
         model = None
         if args.workload == "learned":
-            model = fif.Model(path=args.model, max_batch=1024)
+            model = fif.Model(path=args.model, max_batch=min(len(lengths), 4096))
             plan.set_proposal(model)
         for _ in range(args.warmup):
             plan.run(packed, delta, out=out)

@@ -121,7 +121,7 @@ void forward(fif_model* m, const bf16* x, int B, const float* targets, hipStream
     for (int l = 0; l < kNetLayers; ++l) {
         const int lin = net_len_in(l);
         const int rows = B * (lin / 2);
-        const unsigned grid = (unsigned)((rows + 63) / 64);
+        const unsigned grid = (unsigned)((rows + kNetRowsWG - 1) / kNetRowsWG);
         const float* bias = m->p + net_w_off(l) + net_kf(l) * kNetCh;
         if (l == 0)
             k_conv_fwd<kNetCin0><<<grid, kNetThreads, 0, s>>>(in, lin, m->W.wf[l], bias, m->act[l], rows);
@@ -154,7 +154,7 @@ void backward(fif_model* m, const bf16* x, int B, hipStream_t s)
                                                        m->g + net_w_off(l));
         if (l > 0) {
             const int rows_in = B * lin;
-            k_conv_bwd_data<<<(unsigned)((rows_in + 63) / 64), kNetThreads, 0, s>>>(dz, lin, m->W.wd[l],
+            k_conv_bwd_data<<<(unsigned)((rows_in + kNetRowsWG - 1) / kNetRowsWG), kNetThreads, 0, s>>>(dz, lin, m->W.wd[l],
                                                                                    m->act[l - 1], other, rows_in);
             std::swap(dz, other);
         }

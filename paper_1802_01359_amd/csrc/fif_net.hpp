@@ -24,7 +24,11 @@ namespace fif {
 
 // z[row, o] = bias[o] + sum_k A[row, k] Wf[o, k], A[row, t*CIN + c] =
 // in[b, 2q + t - 3, c] (row = b*lout + q), out = bf16(max(z, 0)).
-// Wf: bf16 [64][KP] (k >= 7*CIN zero).  64 rows per workgroup, 16 per wave.
+// Wf: bf16 [64][KP] (k >= 7*CIN zero).  kNetRowsWG rows per workgroup; each
+// wave owns 64 rows x 64 channels (4 x 4 tiles of 16 x 16), so every weight
+// operand it loads feeds four MFMAs.
+constexpr int kNetRowsWG = 256;
+
 template <int CIN>
 __global__ __launch_bounds__(kNetThreads) void k_conv_fwd(const bf16* __restrict__ in, int lin,
                                                          const bf16* __restrict__ wf,
@@ -34,27 +38,37 @@ __global__ __launch_bounds__(kNetThreads) void k_conv_fwd(const bf16* __restrict
     constexpr int KF = kNetKw * CIN, KP = (KF + 31) / 32 * 32;
     const int lout = lin / 2;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int r0 = blockIdx.x * 64 + wave * 16;
-    const int row = r0 + (lane & 15);
+    const int r0 = blockIdx.x * kNetRowsWG + wave * 64;
     const int kq = (lane >> 4) * 8;
-    const bool live = row < nrows;
-    const int b = live ? row / lout : 0;
-    const int q = live ? row - b * lout : 0;
-    const bf16* base = in + (int64_t)b * lin * CIN;
-    f32x4 acc[4];
+    const bf16* base[4];
+    int qv[4];
+    bool live[4];
 #pragma unroll
-    for (int n = 0; n < 4; ++n) acc[n] = (f32x4){0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
+    for (int m = 0; m < 4; ++m) {
+        const int row = r0 + m * 16 + (lane & 15);
+        live[m] = row < nrows;
+        const int b = live[m] ? row / lout : 0;
+        qv[m] = live[m] ? row - b * lout : 0;
+        base[m] = in + (int64_t)b * lin * CIN;
+    }
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int n = 0; n < 4; ++n) acc[m][n] = (f32x4){0.f, 0.f, 0.f, 0.f};
     for (int k0 = 0; k0 < KP; k0 += 32) {
         const int k = k0 + kq;
         const int t = k / CIN, c = k - t * CIN;
-        const int p = 2 * q + t - 3;
-        bf16x8 a = bf16x8_zero();
-        if (live && t < kNetKw && p >= 0 && p < lin) a = *(const bf16x8*)(base + (int64_t)p * CIN + c);
+        bf16x8 w[4];
 #pragma unroll
-        for (int n = 0; n < 4; ++n) {
-            const bf16x8 w = *(const bf16x8*)(wf + (n * 16 + (lane & 15)) * KP + k);
-            acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w, acc[n], 0, 0, 0);
+        for (int n = 0; n < 4; ++n) w[n] = *(const bf16x8*)(wf + (n * 16 + (lane & 15)) * KP + k);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int p = 2 * qv[m] + t - 3;
+            bf16x8 a = bf16x8_zero();
+            if (live[m] && t < kNetKw && p >= 0 && p < lin) a = *(const bf16x8*)(base[m] + (int64_t)p * CIN + c);
+#pragma unroll
+            for (int n = 0; n < 4; ++n) acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w[n], acc[m][n], 0, 0, 0);
         }
     }
 #pragma unroll
@@ -62,17 +76,20 @@ __global__ __launch_bounds__(kNetThreads) void k_conv_fwd(const bf16* __restrict
         const int col = n * 16 + (lane & 15);
         const float bv = bias[col];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int r = r0 + 4 * (lane >> 4) + i;
-            if (r < nrows) out[(int64_t)r * kNetCh + col] = (bf16)fmaxf(acc[n][i] + bv, 0.f);
-        }
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = r0 + m * 16 + 4 * (lane >> 4) + i;
+                if (r < nrows) out[(int64_t)r * kNetCh + col] = (bf16)fmaxf(acc[m][n][i] + bv, 0.f);
+            }
     }
 }
 
 // Gradient with respect to the input of a 64-channel layer, masked by the
 // input's own ReLU: dprev[b, p, c] = bf16([act[b, p, c] > 0] * sum_{t, o}
 // dz[b, (p + 3 - t)/2, o] W[t, c, o]) over the t with p + 3 - t even and
-// inside the output.  Wd: bf16 [64 c][7*64] (k = t*64 + o).
+// inside the output.  Wd: bf16 [64 c][7*64] (k = t*64 + o).  Same tiling as
+// k_conv_fwd.
 __global__ __launch_bounds__(kNetThreads) void k_conv_bwd_data(const bf16* __restrict__ dz, int lin,
                                                               const bf16* __restrict__ wd,
                                                               const bf16* __restrict__ act,
@@ -81,42 +98,54 @@ __global__ __launch_bounds__(kNetThreads) void k_conv_bwd_data(const bf16* __res
     constexpr int KP = kNetKw * kNetCh;
     const int lout = lin / 2;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int r0 = blockIdx.x * 64 + wave * 16;
-    const int row = r0 + (lane & 15);
+    const int r0 = blockIdx.x * kNetRowsWG + wave * 64;
     const int kq = (lane >> 4) * 8;
-    const bool live = row < nrows;
-    const int b = live ? row / lin : 0;
-    const int p = live ? row - b * lin : 0;
-    const bf16* base = dz + (int64_t)b * lout * kNetCh;
-    f32x4 acc[4];
+    const bf16* base[4];
+    int pv[4];
+    bool live[4];
 #pragma unroll
-    for (int n = 0; n < 4; ++n) acc[n] = (f32x4){0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
+    for (int m = 0; m < 4; ++m) {
+        const int row = r0 + m * 16 + (lane & 15);
+        live[m] = row < nrows;
+        const int b = live[m] ? row / lin : 0;
+        pv[m] = live[m] ? row - b * lin : 0;
+        base[m] = dz + (int64_t)b * lout * kNetCh;
+    }
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int n = 0; n < 4; ++n) acc[m][n] = (f32x4){0.f, 0.f, 0.f, 0.f};
     for (int k0 = 0; k0 < KP; k0 += 32) {
         const int k = k0 + kq;
         const int t = k >> 6, o = k & 63;
-        const int num = p + 3 - t;
-        const int x = num >> 1;
-        bf16x8 a = bf16x8_zero();
-        if (live && num >= 0 && (num & 1) == 0 && x < lout) a = *(const bf16x8*)(base + (int64_t)x * kNetCh + o);
+        bf16x8 w[4];
 #pragma unroll
-        for (int n = 0; n < 4; ++n) {
-            const bf16x8 w = *(const bf16x8*)(wd + (n * 16 + (lane & 15)) * KP + k);
-            acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w, acc[n], 0, 0, 0);
+        for (int n = 0; n < 4; ++n) w[n] = *(const bf16x8*)(wd + (n * 16 + (lane & 15)) * KP + k);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int num = pv[m] + 3 - t;
+            const int x = num >> 1;
+            bf16x8 a = bf16x8_zero();
+            if (live[m] && num >= 0 && (num & 1) == 0 && x < lout) a = *(const bf16x8*)(base[m] + (int64_t)x * kNetCh + o);
+#pragma unroll
+            for (int n = 0; n < 4; ++n) acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w[n], acc[m][n], 0, 0, 0);
         }
     }
 #pragma unroll
     for (int n = 0; n < 4; ++n) {
         const int col = n * 16 + (lane & 15);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int r = r0 + 4 * (lane >> 4) + i;
-            if (r < nrows) {
-                const int64_t e = (int64_t)r * kNetCh + col;
-                const float g = (float)act[e] > 0.f ? acc[n][i] : 0.f;
-                dprev[e] = (bf16)g;
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = r0 + m * 16 + 4 * (lane >> 4) + i;
+                if (r < nrows) {
+                    const int64_t e = (int64_t)r * kNetCh + col;
+                    const float g = (float)act[e] > 0.f ? acc[m][n][i] : 0.f;
+                    dprev[e] = (bf16)g;
+                }
             }
-        }
     }
 }
 
