@@ -119,6 +119,7 @@ struct fif_plan {
     Work *d_btile = nullptr, *d_count = nullptr;
     double* d_dtab = nullptr;
     double2* d_ctab = nullptr;
+    int32_t* d_itab = nullptr;
     // workspace layout (byte offsets)
     size_t ws_state = 0, ws_spec0 = 0, ws_spec1 = 0, ws_inter = 0, ws_parts = 0, ws_psum = 0, ws_gscr = 0,
            ws_bigs = 0, ws_bpart = 0, ws_resid = 0, ws_feat = 0, ws_prop = 0, ws_total = 0;
@@ -228,6 +229,7 @@ fif_status plan_length(int64_t N, LenPlan& lp)
     lp.TR = (int32_t)largest_divisor_at_most(lp.N2, kTileCap / lp.N1);
     // mirror-paired column tiles need N1, N2 and the tile width even
     lp.paired = (lp.N1 % 2 == 0 && lp.N2 % 2 == 0 && lp.TC % 2 == 0) ? 1 : 0;
+    lp.spec_perm = lp.paired;
     int64_t split = 1;
     int shift = 0;
     while (split * split < N) {
@@ -319,7 +321,7 @@ fif_status fif_plan_create(fif_plan** out, const int64_t* lengths, int32_t B, in
     HIP_TRY(hipGetDevice(&p->device));
 
     // tables: sines (doubles) and twiddles (complex), laid out per length
-    int64_t dcount = 0, ccount = 0;
+    int64_t dcount = 0, ccount = 0, icount = 0;
     struct RootReq { int64_t off, den, count, stride; };
     std::vector<RootReq> roots;
     std::vector<std::pair<int64_t, int64_t>> sins;  // (offset, N)
@@ -340,6 +342,12 @@ fif_status fif_plan_create(fif_plan** out, const int64_t* lengths, int32_t B, in
         lp.isin_off = dcount;
         dcount += lp.N / 2 + 1;
         add_sub(lp.f1);
+        if (lp.spec_perm) {
+            lp.bin_off = icount;
+            icount += lp.N / 2 + 1;
+            lp.pos_off = icount;
+            icount += lp.N / 2 + 1;
+        }
         if (lp.two_pass) {
             add_sub(lp.f2);
             lp.big_lo_off = ccount;
@@ -501,10 +509,19 @@ fif_status fif_plan_create(fif_plan** out, const int64_t* lengths, int32_t B, in
     HIP_TRY(hipMemcpy(p->dmeta.p, host.data(), mo, hipMemcpyHostToDevice));
 
     // tables, computed on the device in FP64
-    const size_t tab_bytes = align_up(sizeof(double) * (size_t)dcount, 256) + sizeof(double2) * (size_t)ccount + 256;
+    const size_t c_at = align_up(sizeof(double) * (size_t)dcount, 256);
+    const size_t i_at = align_up(c_at + sizeof(double2) * (size_t)ccount, 256);
+    const size_t tab_bytes = i_at + sizeof(int32_t) * (size_t)icount + 256;
     if (hipMalloc(&p->dtabs.p, tab_bytes) != hipSuccess) return fail(FIF_ERR_NOMEM, "plan table allocation failed");
     p->d_dtab = (double*)p->dtabs.p;
-    p->d_ctab = (double2*)((char*)p->dtabs.p + align_up(sizeof(double) * (size_t)dcount, 256));
+    p->d_ctab = (double2*)((char*)p->dtabs.p + c_at);
+    p->d_itab = (int32_t*)((char*)p->dtabs.p + i_at);
+    for (size_t i = 0; i < p->lens.size(); ++i) {
+        const LenPlan& lp = p->lens[i];
+        if (!lp.spec_perm) continue;
+        const int64_t cnt = lp.N / 2 + 1;
+        k_fill_specmap<<<(unsigned)((cnt + 255) / 256), 256>>>(p->d_lens + i, p->d_itab);
+    }
     for (auto& s : sins) {
         const int64_t cnt = s.second / 2 + 1;
         k_fill_sin<<<(unsigned)((cnt + 255) / 256), 256>>>(p->d_dtab + s.first, s.second, cnt);
@@ -600,6 +617,7 @@ Bound bind(const fif_plan* p, void* ws, double delta, fif_imf_info* info)
     A.st = b.state;
     A.dtab = p->d_dtab;
     A.ctab = p->d_ctab;
+    A.itab = p->d_itab;
     A.spec0 = (double2*)(w + p->ws_spec0);
     A.spec1 = (double2*)(w + p->ws_spec1);
     A.inter = (double2*)(w + p->ws_inter);
@@ -615,6 +633,7 @@ Bound bind(const fif_plan* p, void* ws, double delta, fif_imf_info* info)
     S.parts = A.parts;
     S.psum = (const double*)(w + p->ws_psum);
     S.dtab = p->d_dtab;
+    S.itab = p->d_itab;
     S.spec0 = A.spec0;
     S.spec1 = A.spec1;
     S.gscr = (float*)(w + p->ws_gscr);
@@ -703,6 +722,8 @@ void launch_scan(const fif_plan* p, Bound& b, int t, void* ws, hipStream_t s)
             Timed tm(p, "features", s);
             FeatArgs F;
             F.sigs = p->d_sigs;
+            F.lens = p->d_lens;
+            F.itab = p->d_itab;
             F.st = S.st;
             F.spec0 = S.spec0;
             F.spec1 = S.spec1;

@@ -171,6 +171,8 @@ __device__ __forceinline__ void bscan_tile_sums(const ScanArgs& A, const SigDesc
         }
     } else {
         const Lam lw = make_lam(lp, A.dtab, G->L);
+        // position -> bin table of this length, read once (null: bin order)
+        const int32_t* btab = lp.spec_perm ? A.itab + lp.bin_off : nullptr;
         const double pscale = G->pscale;
         for (int c = 0; c < nc; c += 2) {
             const int64_t e0 = G->cand[c] - 1;
@@ -179,9 +181,10 @@ __device__ __forceinline__ void bscan_tile_sums(const ScanArgs& A, const SigDesc
             for (int q = 0; q < BPT; ++q) {
                 const int j = j0 + tid + q * T;
                 if (j > nh) break;
-                const double2 z = R[j];
-                const double P = ((2 * (int64_t)j == d.N) ? 1.0 : 2.0) * (z.x * z.x + z.y * z.y) * pscale;
-                const double lam = lambda_at(j, lw);
+                const double2 z = R[j];                // storage position j
+                const int64_t jb = (btab ? (int64_t)btab[j] : (int64_t)j);    // its bin
+                const double P = ((2 * jb == d.N) ? 1.0 : 2.0) * (z.x * z.x + z.y * z.y) * pscale;
+                const double lam = lambda_at(jb, lw);
                 const double l2 = lam * lam;
                 const double mu = (1.0 - lam) * (1.0 - lam);
                 double x0, x1 = 0.0;
@@ -367,13 +370,16 @@ __global__ __launch_bounds__(T) void k_bscan_round(ScanArgs A, const Work* __res
         float* bv = av + nh;
         const double2* R = ((A.t & 1) ? A.spec1 : A.spec0) + d.spec_off;
         const Lam lw = make_lam(lp, A.dtab, G->L);
+        // position -> bin table of this length, read once (null: bin order)
+        const int32_t* btab = lp.spec_perm ? A.itab + lp.bin_off : nullptr;
         const double pscale = G->pscale;
         for (int q = 0; q < BPT; ++q) {
             const int j = 1 + w.tile * kBigTile + threadIdx.x + q * T;
             if (j > nh) break;
-            const double2 z = R[j];
-            const double P = ((2 * (int64_t)j == d.N) ? 1.0 : 2.0) * (z.x * z.x + z.y * z.y) * pscale;
-            const double lam = lambda_at(j, lw);
+            const double2 z = R[j];                    // storage position j
+            const int64_t jb = (btab ? (int64_t)btab[j] : (int64_t)j);        // its bin
+            const double P = ((2 * jb == d.N) ? 1.0 : 2.0) * (z.x * z.x + z.y * z.y) * pscale;
+            const double lam = lambda_at(jb, lw);
             bv[j - 1] = (float)P;
             av[j - 1] = (float)(P * lam * lam);
             tau[j - 1] = 2.8853900817779268f * log1pf(-(float)lam);

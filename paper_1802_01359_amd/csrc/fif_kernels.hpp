@@ -354,8 +354,34 @@ __global__ void k_fill_roots(double2* __restrict__ out, int64_t den, int64_t cou
 }
 
 // four-step twiddle exp(-+2 pi i a / N), a < N, from the split tables
+// Scalar fields of a length plan held in registers by the step kernels (the
+// plan itself sits in global memory, which their stores might alias, so
+// reading it inside a loop would reload it).
+struct PlanRegs {
+    int64_t N;
+    int N1, N2, TC, TR, paired, spec_perm;
+    int64_t big_lo_off, big_hi_off;
+    int big_split, big_shift;
+};
+__device__ __forceinline__ PlanRegs plan_regs(const LenPlan& lp)
+{
+    PlanRegs r;
+    r.N = lp.N;
+    r.N1 = lp.N1;
+    r.N2 = lp.N2;
+    r.TC = lp.TC;
+    r.TR = lp.TR;
+    r.paired = lp.paired;
+    r.spec_perm = lp.spec_perm;
+    r.big_lo_off = lp.big_lo_off;
+    r.big_hi_off = lp.big_hi_off;
+    r.big_split = lp.big_split;
+    r.big_shift = lp.big_shift;
+    return r;
+}
+
 template <bool INV>
-__device__ __forceinline__ double2 big_twiddle(const LenPlan& lp, const double2* __restrict__ tabs, int64_t a)
+__device__ __forceinline__ double2 big_twiddle(const PlanRegs& lp, const double2* __restrict__ tabs, int64_t a)
 {
     const int ai = (int)a;
     double2 w = cmul(tabs[lp.big_hi_off + (ai >> lp.big_shift)], tabs[lp.big_lo_off + (ai & (lp.big_split - 1))]);
@@ -415,6 +441,7 @@ struct StepArgs {
     SigState* st;
     const double* dtab;    // sine tables
     const double2* ctab;   // twiddle tables
+    const int32_t* itab;   // storage position <-> bin maps
     double2* spec0;
     double2* spec1;
     double2* inter;
@@ -528,7 +555,7 @@ __global__ __launch_bounds__(kFftThreads) void k_single(StepArgs A, const InT* _
 // at (N1-c, N2-1-r) for c != 0 and at (0, N2-r) for c = 0; bin N/2 sits at
 // (0, N2/2).  Each bin is then read once and its gain computed once.
 // Otherwise tiles are TC consecutive columns and each element reads its bin.
-__device__ __forceinline__ int pass1_col(const LenPlan& lp, int tile, int s)
+__device__ __forceinline__ int pass1_col(const PlanRegs& lp, int tile, int s)
 {
     if (!lp.paired) return tile * lp.TC + s;
     const int h = lp.TC >> 1;
@@ -536,6 +563,112 @@ __device__ __forceinline__ int pass1_col(const LenPlan& lp, int tile, int s)
     if (s < h) return u;
     return u == 0 ? (lp.N1 >> 1) : lp.N1 - u;
 }
+__device__ __forceinline__ int pass1_col(const LenPlan& lp, int tile, int s)
+{
+    return pass1_col(plan_regs(lp), tile, s);
+}
+
+// Storage order of the half spectrum (bins 0..N/2).  Two-pass paired plans
+// keep it in pass-1 tile order so that pass 1 reads and writes one
+// contiguous run per tile: the bins owned by tile t (c + N1*r for its TC
+// columns c, slot s, and r < N2/2) sit at t*TC*N2/2 + r*TC + s; bin N/2 stays
+// last.  Other plans use bin order.
+__device__ __forceinline__ int64_t spec_pos(const LenPlan& lp, int64_t j)
+{
+    if (!lp.spec_perm) return j;
+    const int nh = (int)(lp.N / 2);
+    if (j == nh) return nh;
+    const int N1 = lp.N1, h = lp.TC >> 1;
+    const int r = (int)j / N1, c = (int)j - r * N1;
+    int u, s0;
+    if (2 * c < N1) {
+        u = c;
+        s0 = 0;
+    } else {
+        u = (2 * c == N1) ? 0 : N1 - c;
+        s0 = h;
+    }
+    const int t = u / h;
+    return (int64_t)t * (lp.TC * (lp.N2 >> 1)) + (int64_t)r * lp.TC + s0 + (u - t * h);
+}
+
+// Bin stored at position p (inverse of spec_pos).
+__device__ __forceinline__ int64_t spec_bin(const LenPlan& lp, int64_t p)
+{
+    if (!lp.spec_perm) return p;
+    const int nh = (int)(lp.N / 2);
+    if (p == nh) return nh;
+    const int owners = lp.TC * (lp.N2 >> 1);
+    const int t = (int)p / owners;
+    const int f = (int)p - t * owners;
+    const int r = f / lp.TC, s = f - r * lp.TC;
+    return pass1_col(lp, t, s) + (int64_t)lp.N1 * r;
+}
+
+// spec_pos by reciprocal division, exact for j < 2^22 (fdivmod's one-step
+// correction), for the one-workgroup scan (j <= 32768), which walks the bins
+// in order: the per-bin sine tables are then read coalesced and the
+// spectrum in runs of TC/2 bins.
+// Copies of the plan fields it needs (kept in registers inside bin loops).
+struct SpecMap {
+    FastDiv n1, h;
+    int perm, nh, N1, hh, TC, owners;
+};
+__device__ __forceinline__ SpecMap make_specmap(const LenPlan& lp)
+{
+    SpecMap m;
+    m.perm = lp.spec_perm;
+    m.nh = (int)(lp.N / 2);
+    m.N1 = lp.N1;
+    m.hh = lp.TC >> 1;
+    m.TC = lp.TC;
+    m.owners = lp.TC * (lp.N2 >> 1);
+    m.n1 = fastdiv(m.perm ? m.N1 : 1);
+    m.h = fastdiv(m.perm ? m.hh : 1);
+    return m;
+}
+__device__ __forceinline__ int pos_small(const SpecMap& m, int j)
+{
+    if (!m.perm || j == m.nh) return j;
+    int c;
+    const int r = fdivmod(j, m.n1, c);
+    int u, s0;
+    if (2 * c < m.N1) {
+        u = c;
+        s0 = 0;
+    } else {
+        u = (2 * c == m.N1) ? 0 : m.N1 - c;
+        s0 = m.hh;
+    }
+    int ur;
+    const int t = fdivmod(u, m.h, ur);
+    return t * m.owners + r * m.TC + s0 + ur;
+}
+
+// Table forms: itab[bin_off + p] = bin at position p, itab[pos_off + j] =
+// position of bin j (filled once per plan by k_fill_specmap).
+__device__ __forceinline__ int64_t bin_at(const LenPlan& lp, const int32_t* __restrict__ itab, int64_t p)
+{
+    return lp.spec_perm ? (int64_t)itab[lp.bin_off + p] : p;
+}
+__device__ __forceinline__ int64_t pos_of(const LenPlan& lp, const int32_t* __restrict__ itab, int64_t j)
+{
+    return lp.spec_perm ? (int64_t)itab[lp.pos_off + j] : j;
+}
+
+__global__ void k_fill_specmap(const LenPlan* __restrict__ lpp, int32_t* __restrict__ itab)
+{
+    const LenPlan& lp = *lpp;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p > lp.N / 2) return;
+    const int64_t j = spec_bin(lp, p);
+    itab[lp.bin_off + p] = (int32_t)j;
+    itab[lp.pos_off + j] = (int32_t)p;
+}
+
+// The four-step intermediate is stored tile-major: pass-1 tile t writes its
+// TC x N2 block (row r', slot s at t*TC*N2 + r'*TC + s) as one run; pass 2
+// gathers, for its TR rows, a TR x TC run from every pass-1 tile.
 
 template <int MODE, typename InT>
 __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __restrict__ x)
@@ -544,6 +677,7 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
     const Work w = A.work[blockIdx.x];
     const SigDesc d = A.sigs[w.sig];
     const LenPlan& lp = A.lens[d.len_id];
+    const PlanRegs pr = plan_regs(lp);
     const int64_t N = d.N;
     const int N1 = lp.N1, N2 = lp.N2, TC = lp.TC;
     SigState* S = A.st + w.sig;
@@ -555,7 +689,7 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
         for (int f = threadIdx.x; f < total; f += kFftThreads) {
             int s;
             const int r = fdivmod(f, ftc, s);
-            lds[f] = make_double2((double)x[d.off + pass1_col(lp, w.tile, s) + (int64_t)N1 * r], 0.0);
+            lds[f] = make_double2((double)x[d.off + pass1_col(pr, w.tile, s) + (int64_t)N1 * r], 0.0);
         }
     } else {
         const int buf = (MODE == MODE_STEP) ? (A.t & 1) : S->final_buf;
@@ -567,18 +701,35 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
         if (lp.paired) {
             const int h = TC >> 1;
             const int owners = TC * (N2 >> 1);
-            for (int f = threadIdx.x; f <= owners; f += kFftThreads) {
+            // the tile's bins are one contiguous run (tile order, see
+            // spec_pos); all of a thread's loads are issued first
+            constexpr int PQ = kTileCap / 2 / kFftThreads + 1;
+            double2 vv[PQ];
+            const int64_t pbase = (int64_t)w.tile * owners;
+#pragma unroll
+            for (int q = 0; q < PQ; ++q) {
+                const int f = threadIdx.x + q * kFftThreads;
+                vv[q] = make_double2(0.0, 0.0);
+                if (f < owners)
+                    vv[q] = Rin[pbase + f];
+                else if (f == owners && w.tile == 0)
+                    vv[q] = Rin[N >> 1];
+            }
+#pragma unroll
+            for (int q = 0; q < PQ; ++q) {
+                const int f = threadIdx.x + q * kFftThreads;
+                if (f > owners || (f == owners && w.tile != 0)) break;
                 int s, r;
                 if (f < owners) {
                     r = fdivmod(f, ftc, s);
                 } else {
-                    if (w.tile != 0) break;
                     s = 0;          // bin N/2 at (0, N2/2)
                     r = N2 >> 1;
                 }
-                const int c = pass1_col(lp, w.tile, s);
+                const int c = pass1_col(pr, w.tile, s);
                 const int64_t k = c + (int64_t)N1 * r;
-                const double2 v = Rin[k];
+                const int64_t pk = (f < owners) ? pbase + f : (N >> 1);
+                const double2 v = vv[q];
                 double g = 0.0;
                 if (MODE == MODE_STEP) g = gain_pow(lambda_at(k, lw), m);
                 lds[r * TC + s] = step_input(v, false, g, invN);
@@ -593,14 +744,14 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
                     }
                     if (!(c == 0 && r == 0)) lds[mr * TC + ms] = step_input(v, true, g, invN);
                 }
-                if (MODE == MODE_STEP) Rout[k] = cscale(v, 1.0 - g);
+                if (MODE == MODE_STEP) Rout[pk] = cscale(v, 1.0 - g);
             }
         } else {
             const int64_t nh = N / 2;
             for (int f = threadIdx.x; f < total; f += kFftThreads) {
                 int s;
                 const int r = fdivmod(f, ftc, s);
-                const int64_t k = pass1_col(lp, w.tile, s) + (int64_t)N1 * r;
+                const int64_t k = pass1_col(pr, w.tile, s) + (int64_t)N1 * r;
                 const bool mirror = k > nh;
                 const int64_t j = mirror ? N - k : k;
                 const double2 v = Rin[j];
@@ -620,15 +771,15 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
     for (int f = threadIdx.x; f < total; f += kFftThreads) {
         int s;
         const int rp = fdivmod(f, ftc, s);
-        const int c = pass1_col(lp, w.tile, s);
+        const int c = pass1_col(pr, w.tile, s);
         const int64_t a = (int64_t)rp * c;
         double2 v = lds[f];
         if (a != 0) {
-            const double2 tw = (MODE == MODE_FORWARD) ? big_twiddle<false>(lp, A.ctab, a)
-                                                      : big_twiddle<true>(lp, A.ctab, a);
+            const double2 tw = (MODE == MODE_FORWARD) ? big_twiddle<false>(pr, A.ctab, a)
+                                                      : big_twiddle<true>(pr, A.ctab, a);
             v = cmul(v, tw);
         }
-        Y[(int64_t)rp * N1 + c] = v;
+        Y[(int64_t)w.tile * total + f] = v;
     }
 }
 
@@ -647,12 +798,13 @@ __global__ __launch_bounds__(kFftThreads) void k_pass2(StepArgs A, const InT* __
     const Work w = A.work[blockIdx.x];
     const SigDesc d = A.sigs[w.sig];
     const LenPlan& lp = A.lens[d.len_id];
+    const PlanRegs pr = plan_regs(lp);
     const int64_t N = d.N;
     const int N1 = lp.N1, N2 = lp.N2, TR = lp.TR;
     const int r0 = w.tile * TR;
     SigState* S = A.st + w.sig;
     const int total = TR * N1;
-    const FastDiv ftr = fastdiv(TR), fn1 = fastdiv(N1);
+    const FastDiv ftr = fastdiv(TR);
     if (MODE == MODE_STEP && !S->active) {
         OutT* row = imfs + (int64_t)A.max_imfs * d.off + (int64_t)A.t * N;
         for (int f = threadIdx.x; f < total; f += kFftThreads) {
@@ -672,10 +824,34 @@ __global__ __launch_bounds__(kFftThreads) void k_pass2(StepArgs A, const InT* __
         return;
     }
     const double2* Y = A.inter + d.inter_off;
-    for (int f = threadIdx.x; f < total; f += kFftThreads) {
-        int c;
-        const int rl = fdivmod(f, fn1, c);
-        lds[c * TR + rl] = Y[(int64_t)(r0 + rl) * N1 + c];
+    {
+        // e = (t * TR + rl) * TC + s: one TR x TC run per pass-1 tile t
+        const int TC = lp.TC;
+        const FastDiv ftc = fastdiv(TC);
+        const int64_t blk = (int64_t)TC * N2;
+        constexpr int GQ = kTileCap / kFftThreads;
+        double2 yv[GQ];
+#pragma unroll
+        for (int q = 0; q < GQ; ++q) {
+            const int e = threadIdx.x + q * kFftThreads;
+            yv[q] = make_double2(0.0, 0.0);
+            if (e < total) {
+                int s, rl;
+                const int u = fdivmod(e, ftc, s);
+                const int t = fdivmod(u, ftr, rl);
+                yv[q] = Y[(int64_t)t * blk + (int64_t)(r0 + rl) * TC + s];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < GQ; ++q) {
+            const int e = threadIdx.x + q * kFftThreads;
+            if (e < total) {
+                int s, rl;
+                const int u = fdivmod(e, ftc, s);
+                const int t = fdivmod(u, ftr, rl);
+                lds[pass1_col(pr, t, s) * TR + rl] = yv[q];
+            }
+        }
     }
     __syncthreads();
     if (MODE == MODE_FORWARD)
@@ -689,7 +865,7 @@ __global__ __launch_bounds__(kFftThreads) void k_pass2(StepArgs A, const InT* __
             int rl;
             const int cp = fdivmod(f, ftr, rl);
             const int64_t n = (int64_t)N2 * cp + r0 + rl;
-            if (n <= nh) out[n] = lds[f];
+            if (n <= nh) out[spec_pos(lp, n)] = lds[f];
         }
         return;
     }
@@ -746,6 +922,7 @@ struct ScanArgs {
     const RunState* parts;
     const double* psum;       // per-tile sums of the input (first step)
     const double* dtab;
+    const int32_t* itab;      // storage position <-> bin maps
     const double2* spec0;
     const double2* spec1;
     float* gscr;              // FP32 scratch of the multi-workgroup scan (SigDesc::gs_off)
@@ -904,25 +1081,46 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
     //      lambda_0 = 1 contributes to m = 1 only) ----
     float tau_r[NR], b_r[NR];
     extern __shared__ float lds_a[];
+    const SpecMap smap = make_specmap(lp);
     auto weight = [&](int j) -> double { return (2 * (int64_t)j == N) ? 1.0 : 2.0; };
-    auto sweep_bin = [&](int j, float& tau, float& av, float& bv) {
-        const double2 v = R[j];
-        const double P = weight(j) * (v.x * v.x + v.y * v.y) * pscale;
-        const double lam = lambda_at(j, lw);
+    // v: spectrum of bin jb
+    auto sweep_bin = [&](double2 v, int64_t jb, float& tau, float& av, float& bv) {
+        const double P = weight(jb) * (v.x * v.x + v.y * v.y) * pscale;
+        const double lam = lambda_at(jb, lw);
         const float lf = (float)lam;
         bv = (float)P;
         av = (float)(P * lam * lam);
         tau = 2.8853900817779268f * log1pf(-lf);  // 2 log2(1 - lambda)
     };
+    // bins in groups of SG: the group's loads are issued together (memory
+    // parallelism), the FP64 work of different groups is kept apart
+    // (register pressure)
+    constexpr int SG = 8;
+    static_assert(NR % SG == 0, "sweep groups");
 #pragma unroll
-    for (int i = 0; i < NR; ++i) {
-        const int j = 1 + tid + i * T;
-        float av = 0.f;
-        tau_r[i] = 0.f;
-        b_r[i] = 0.f;
-        if (j <= nh) sweep_bin(j, tau_r[i], av, b_r[i]);
-        lds_a[i * T + tid] = av;
-        // keep the FP64 work of different bins apart (register pressure)
+    for (int i0 = 0; i0 < NR; i0 += SG) {
+        double2 v[SG];
+        int64_t jb[SG];
+#pragma unroll
+        for (int g = 0; g < SG; ++g) {
+            const int j = 1 + tid + (i0 + g) * T;
+            v[g] = make_double2(0.0, 0.0);
+            jb[g] = 0;
+            if (j <= nh) {
+                v[g] = R[pos_small(smap, j)];
+                jb[g] = j;
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < SG; ++g) {
+            const int i = i0 + g;
+            const int j = 1 + tid + i * T;
+            float av = 0.f;
+            tau_r[i] = 0.f;
+            b_r[i] = 0.f;
+            if (j <= nh) sweep_bin(v[g], jb[g], tau_r[i], av, b_r[i]);
+            lds_a[i * T + tid] = av;
+        }
         __builtin_amdgcn_sched_barrier(0);
     }
     const double P0 = (R[0].x * R[0].x + R[0].y * R[0].y) * pscale;
@@ -1069,10 +1267,27 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
     auto sd64 = [&](int64_t m, double& sd_m, double& sd_mm1) {
         double v[4] = {0.0, 0.0, 0.0, 0.0};
         const int64_t e = m - 2;  // exponent of mu at m-1; may be -1
-        for (int j = 1 + tid; j <= nh; j += T) {
-            const double2 z = R[j];
-            const double P = weight(j) * (z.x * z.x + z.y * z.y) * pscale;
-            const double lam = lambda_at(j, lw);
+        constexpr int DG = 4;     // bins whose loads are issued together
+        for (int j0 = 1 + tid; j0 <= nh; j0 += DG * T) {
+          double2 zz[DG];
+          int64_t jj[DG];
+#pragma unroll
+          for (int g = 0; g < DG; ++g) {
+            const int j = j0 + g * T;
+            zz[g] = make_double2(0.0, 0.0);
+            jj[g] = 0;
+            if (j <= nh) {
+                zz[g] = R[pos_small(smap, j)];
+                jj[g] = j;
+            }
+          }
+#pragma unroll
+          for (int g = 0; g < DG; ++g) {
+            if (j0 + g * T > nh) break;
+            const double2 z = zz[g];
+            const int64_t jb = jj[g];
+            const double P = weight(jb) * (z.x * z.x + z.y * z.y) * pscale;
+            const double lam = lambda_at(jb, lw);
             const double l2 = lam * lam;
             const double om = 1.0 - lam;
             double xe;  // mu^e
@@ -1089,6 +1304,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
             v[1] += P * xe;
             v[2] += P * l2 * xm;
             v[3] += P * xm;
+          }
         }
         if (tid == 0) {
             if (m == 1) {

@@ -14,6 +14,8 @@ namespace fif {
 // log2(L)/16, channels 2..7 = 0.  Row `slot` of out (bf16 [.][1024][8]).
 struct FeatArgs {
     const SigDesc* sigs;
+    const LenPlan* lens;
+    const int32_t* itab;
     const SigState* st;
     const double2* spec0;
     const double2* spec1;
@@ -44,7 +46,8 @@ __global__ __launch_bounds__(kNetThreads) void k_features(FeatArgs A)
     const SigState* S = A.st + s;
     if (!S->active) return;
     const SigDesc d = A.sigs[s];
-    const double2* R = ((A.t & 1) ? A.spec1 : A.spec0) + d.spec_off + 1;   // R[u] = bin u + 1
+    const double2* R = ((A.t & 1) ? A.spec1 : A.spec0) + d.spec_off;
+    const LenPlan& lp = A.lens[d.len_id];
     const int64_t H = d.N / 2;
     const int tid = threadIdx.x;
     for (int q = tid; q < kNetFeat; q += kNetThreads) gs[q] = 0.0;
@@ -53,7 +56,7 @@ __global__ __launch_bounds__(kNetThreads) void k_features(FeatArgs A)
         const int n = (int)min((int64_t)kFeatTile, H - t0);
         __syncthreads();
         for (int i = tid; i < n; i += kNetThreads) {
-            const double2 z = R[t0 + i];
+            const double2 z = R[pos_of(lp, A.itab, t0 + i + 1)];   // bin t0 + i + 1
             const double v = z.x * z.x + z.y * z.y;
             pw[i] = v;
             tot[0] += v;

@@ -30,12 +30,13 @@ struct LenPlan {
     int32_t N1, N2;                // N1: pass-2 length (columns), N2: pass-1 length (rows)
     int32_t TC, TR;                // pass-1 column tile, pass-2 row tile
     int32_t paired;                // pass-1 tiles hold mirror column pairs {c, N1-c}
-    int32_t pad0;
+    int32_t spec_perm;             // half spectrum stored in pass-1 tile order (paired plans)
     SubFft f1;                     // length N2 (pass 1) or N (single pass)
     SubFft f2;                     // length N1 (pass 2)
     int64_t sin_off;               // offset (doubles) of sin(pi u/N), u = 0..N/2
     int64_t isin_off;              // offset (doubles) of 1/sin(pi u/N), u = 1..N/2
     int64_t big_lo_off, big_hi_off;// offsets (complex) of the four-step twiddle tables
+    int64_t bin_off, pos_off;      // offsets (int32) of the storage position <-> bin maps
     double invN;                   // 1/N rounded
     int32_t big_split;             // exp(-2 pi i a/N) = hi[a >> shift] * lo[a & (split-1)]
     int32_t big_shift;             // log2(big_split)
