@@ -100,15 +100,24 @@ struct fif_plan {
     std::vector<SigDesc> sigs;
     std::vector<LenPlan> lens;
     std::vector<Work> w_init, w_single, w_p1, w_p2;
-    // four-step work is issued in chunks of signals whose intermediates
-    // share one buffer of at most chunk_bytes (so it can stay cache resident)
-    struct Chunk {
-        int32_t p1_begin, p1_count, p2_begin, p2_count;
-    };
-    std::vector<Chunk> chunks;
-    size_t chunk_bytes = 0;
     std::vector<int32_t> scan_small, scan_big;
     std::vector<Work> w_btile, w_count;
+    // Signal groups: contiguous signal ranges whose outer steps are issued
+    // on separate streams, so that one group's scan (latency bound, one
+    // workgroup per signal) runs beside another group's transforms.  Each
+    // group owns a contiguous sub-range of every work list.
+    struct Range {
+        int32_t begin = 0, count = 0;
+    };
+    struct Group {
+        int32_t s0 = 0, s1 = 0;
+        Range single, p1, p2, ssmall, sbig, btile, count;
+    };
+    std::vector<Group> groups;      // groups[0] is the whole batch when only one
+    Group all;
+    std::vector<hipStream_t> gstreams;   // streams of groups 1..
+    hipEvent_t ev_fork = nullptr;
+    std::vector<hipEvent_t> ev_join;
     size_t lds_single = 0, lds_p1 = 0, lds_p2 = 0;
     // device copies (one allocation)
     DevBuf dmeta, dtabs;
@@ -142,6 +151,9 @@ struct fif_plan {
             pool.push_back(r.b);
         }
         for (auto e : pool) (void)hipEventDestroy(e);
+        for (auto s : gstreams) (void)hipStreamDestroy(s);
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        for (auto e : ev_join) (void)hipEventDestroy(e);
     }
 };
 
@@ -363,17 +375,6 @@ fif_status fif_plan_create(fif_plan** out, const int64_t* lengths, int32_t B, in
     // signals, work lists, workspace sizes
     int64_t off = 0, spec = 0, inter = 0, inter_max = 0, gscr = 0, resid = 0;
     int32_t parts = 0, nbig = 0, btiles = 0;
-    {
-        const char* env = getenv("FIF_CHUNK_BYTES");
-        p->chunk_bytes = env ? (size_t)strtoull(env, nullptr, 10) : 0;
-        if (p->chunk_bytes == 0) p->chunk_bytes = (size_t)1 << 62;
-    }
-    auto close_chunk = [&]() {
-        if (p->chunks.empty()) return;
-        fif_plan::Chunk& c = p->chunks.back();
-        c.p1_count = (int32_t)p->w_p1.size() - c.p1_begin;
-        c.p2_count = (int32_t)p->w_p2.size() - c.p2_begin;
-    };
     for (int32_t b = 0; b < B; ++b) {
         const int64_t N = lengths[b];
         const int32_t lid = len_id[N];
@@ -382,14 +383,6 @@ fif_status fif_plan_create(fif_plan** out, const int64_t* lengths, int32_t B, in
         d.N = N;
         d.off = off;
         d.spec_off = spec;
-        if (lp.two_pass) {
-            const size_t need = sizeof(double2) * (size_t)N;
-            if (p->chunks.empty() || (inter > 0 && sizeof(double2) * (size_t)inter + need > p->chunk_bytes)) {
-                close_chunk();
-                p->chunks.push_back({(int32_t)p->w_p1.size(), 0, (int32_t)p->w_p2.size(), 0});
-                inter = 0;
-            }
-        }
         d.inter_off = lp.two_pass ? inter : 0;
         d.len_id = lid;
         d.part_off = parts;
@@ -440,8 +433,55 @@ fif_status fif_plan_create(fif_plan** out, const int64_t* lengths, int32_t B, in
             p->scan_big.push_back(b);
     }
 
-    close_chunk();
     inter = inter_max;
+
+    // signal groups of about equal sample counts
+    {
+        const char* env = getenv("FIF_GROUPS");
+        int G = env ? atoi(env) : 2;
+        G = std::max(1, std::min(G, std::min(B, 8)));
+        int64_t total = 0;
+        for (int32_t b = 0; b < B; ++b) total += lengths[b];
+        auto sub = [](const std::vector<Work>& v, int32_t s0, int32_t s1) {
+            fif_plan::Range r;
+            const auto lo = std::lower_bound(v.begin(), v.end(), s0, [](const Work& w, int32_t s) { return w.sig < s; });
+            const auto hi = std::lower_bound(v.begin(), v.end(), s1, [](const Work& w, int32_t s) { return w.sig < s; });
+            r.begin = (int32_t)(lo - v.begin());
+            r.count = (int32_t)(hi - lo);
+            return r;
+        };
+        auto subi = [](const std::vector<int32_t>& v, int32_t s0, int32_t s1) {
+            fif_plan::Range r;
+            const auto lo = std::lower_bound(v.begin(), v.end(), s0);
+            const auto hi = std::lower_bound(v.begin(), v.end(), s1);
+            r.begin = (int32_t)(lo - v.begin());
+            r.count = (int32_t)(hi - lo);
+            return r;
+        };
+        auto make_group = [&](int32_t s0, int32_t s1) {
+            fif_plan::Group g;
+            g.s0 = s0;
+            g.s1 = s1;
+            g.single = sub(p->w_single, s0, s1);
+            g.p1 = sub(p->w_p1, s0, s1);
+            g.p2 = sub(p->w_p2, s0, s1);
+            g.btile = sub(p->w_btile, s0, s1);
+            g.count = sub(p->w_count, s0, s1);
+            g.ssmall = subi(p->scan_small, s0, s1);
+            g.sbig = subi(p->scan_big, s0, s1);
+            return g;
+        };
+        p->all = make_group(0, B);
+        int32_t s0 = 0;
+        int64_t acc = 0;
+        for (int g = 0; g < G && s0 < B; ++g) {
+            int32_t s1 = s0;
+            const int64_t target = total * (g + 1) / G;
+            while (s1 < B && (s1 == s0 || acc + lengths[s1] <= target || g == G - 1)) acc += lengths[s1++];
+            p->groups.push_back(make_group(s0, s1));
+            s0 = s1;
+        }
+    }
 
     size_t ws = 0;
     p->ws_state = ws = align_up(ws, 256);
@@ -670,48 +710,49 @@ void launch_init(const fif_plan* p, Bound& b, const T* x, hipStream_t s)
         k_single<MODE_FORWARD, T, T><<<(unsigned)p->w_single.size(), kFftThreads, p->lds_single, s>>>(A, x, nullptr,
                                                                                                      nullptr);
     }
-    for (const auto& c : p->chunks) {
-        A.work = p->d_p1 + c.p1_begin;
+    if (!p->w_p1.empty()) {
+        A.work = p->d_p1;
         {
             Timed tm(p, "pass1_fwd", s);
-            k_pass1<MODE_FORWARD, T><<<(unsigned)c.p1_count, kFftThreads, p->lds_p1, s>>>(A, x);
+            k_pass1<MODE_FORWARD, T><<<(unsigned)p->w_p1.size(), kFftThreads, p->lds_p1, s>>>(A, x);
         }
-        A.work = p->d_p2 + c.p2_begin;
+        A.work = p->d_p2;
         Timed tm(p, "pass2_fwd", s);
-        k_pass2<MODE_FORWARD, T, T><<<(unsigned)c.p2_count, kFftThreads, p->lds_p2, s>>>(A, x, nullptr, nullptr);
+        k_pass2<MODE_FORWARD, T, T><<<(unsigned)p->w_p2.size(), kFftThreads, p->lds_p2, s>>>(A, x, nullptr, nullptr);
     }
 }
 
 // Search for m of every active signal.  With a proposal model or feature
 // recording the step starts (count combine, stop rules, L) run first, then
 // the features, the network and the proposals, then the searches.
-void launch_scan(const fif_plan* p, Bound& b, int t, void* ws, hipStream_t s)
+void launch_scan(const fif_plan* p, Bound& b, int t, void* ws, hipStream_t s, const fif_plan::Group& g)
 {
     ScanArgs S = b.sc;
     S.t = t;
     const bool split = p->model || p->rec;
-    const unsigned nb = (unsigned)p->scan_big.size(), nt = (unsigned)p->w_btile.size();
+    const unsigned nb = (unsigned)g.sbig.count, nt = (unsigned)g.btile.count;
+    const Work* btile = p->d_btile + g.btile.begin;
     const size_t scan_lds = sizeof(float) * kScanBinsPerThread * kScanThreads;
     if (!split) {
-        if (!p->scan_small.empty()) {
-            S.list = p->d_scan_small;
+        if (g.ssmall.count) {
+            S.list = p->d_scan_small + g.ssmall.begin;
             Timed tm(p, "scan", s);
-            k_scan<kScanBinsPerThread, false><<<(unsigned)p->scan_small.size(), kScanThreads, scan_lds, s>>>(S);
+            k_scan<kScanBinsPerThread, false><<<(unsigned)g.ssmall.count, kScanThreads, scan_lds, s>>>(S);
         }
         if (nb) {
             Timed tm(p, "scan_big", s);
-            S.list = p->d_scan_big;
+            S.list = p->d_scan_big + g.sbig.begin;
             k_bscan_prep<kScanThreads><<<nb, kScanThreads, 0, s>>>(S);
         }
     } else {
         {
             Timed tm(p, "scan_prologue", s);
-            if (!p->scan_small.empty()) {
-                S.list = p->d_scan_small;
-                k_scan_prologue<kScanThreads><<<(unsigned)p->scan_small.size(), kScanThreads, 0, s>>>(S);
+            if (g.ssmall.count) {
+                S.list = p->d_scan_small + g.ssmall.begin;
+                k_scan_prologue<kScanThreads><<<(unsigned)g.ssmall.count, kScanThreads, 0, s>>>(S);
             }
             if (nb) {
-                S.list = p->d_scan_big;
+                S.list = p->d_scan_big + g.sbig.begin;
                 k_bscan_prep<kScanThreads><<<nb, kScanThreads, 0, s>>>(S);
             }
         }
@@ -731,35 +772,36 @@ void launch_scan(const fif_plan* p, Bound& b, int t, void* ws, hipStream_t s)
             F.out = feat;
             F.rec = p->rec;
             F.max_imfs = p->max_imfs;
-            k_features<<<(unsigned)p->B, kNetThreads, 0, s>>>(F);
+            F.s0 = g.s0;
+            k_features<<<(unsigned)(g.s1 - g.s0), kNetThreads, 0, s>>>(F);
         }
         if (p->model) {
             Timed tm(p, "propose", s);
             const int mb = model_max_batch(p->model);
-            for (int s0 = 0; s0 < p->B; s0 += mb) {
-                const int n = std::min(mb, p->B - s0);
+            for (int s0 = g.s0; s0 < g.s1; s0 += mb) {
+                const int n = std::min(mb, g.s1 - s0);
                 const float* y = model_infer(p->model, feat + (size_t)s0 * kNetFeat * kNetCin0, n, s);
                 k_propose<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(y, s0, n, p->opt.max_inner, S.st, prop);
             }
             S.prop = prop;
         }
-        if (!p->scan_small.empty()) {
-            S.list = p->d_scan_small;
+        if (g.ssmall.count) {
+            S.list = p->d_scan_small + g.ssmall.begin;
             Timed tm(p, "scan", s);
-            k_scan<kScanBinsPerThread, true><<<(unsigned)p->scan_small.size(), kScanThreads, scan_lds, s>>>(S);
+            k_scan<kScanBinsPerThread, true><<<(unsigned)g.ssmall.count, kScanThreads, scan_lds, s>>>(S);
         }
         if (nb && p->model) {
-            S.list = p->d_scan_big;
+            S.list = p->d_scan_big + g.sbig.begin;
             k_bscan_seed<<<nb, 64, 0, s>>>(S);
         }
     }
     if (nb) {
         Timed tm(p, "scan_big", s);
-        S.list = p->d_scan_big;
-        k_bscan_round<kScanThreads, true><<<nt, kScanThreads, 0, s>>>(S, p->d_btile);
+        S.list = p->d_scan_big + g.sbig.begin;
+        k_bscan_round<kScanThreads, true><<<nt, kScanThreads, 0, s>>>(S, btile);
         k_bscan_decide<<<nb, 64 * kDecideGroups, 0, s>>>(S);
         for (int r = 0; r < kBigRounds; ++r) {
-            k_bscan_round<kScanThreads, false><<<nt, kScanThreads, 0, s>>>(S, p->d_btile);
+            k_bscan_round<kScanThreads, false><<<nt, kScanThreads, 0, s>>>(S, btile);
             k_bscan_decide<<<nb, 64 * kDecideGroups, 0, s>>>(S);
         }
         k_bscan_final<kScanThreads><<<nb, 64, 0, s>>>(S);
@@ -767,30 +809,31 @@ void launch_scan(const fif_plan* p, Bound& b, int t, void* ws, hipStream_t s)
 }
 
 template <typename T>
-void launch_step(const fif_plan* p, Bound& b, int t, const T* x, T* imfs, void* ws, hipStream_t s)
+void launch_step(const fif_plan* p, Bound& b, int t, const T* x, T* imfs, void* ws, hipStream_t s,
+                 const fif_plan::Group& g)
 {
-    launch_scan(p, b, t, ws, s);
+    launch_scan(p, b, t, ws, s, g);
     StepArgs A = b.sa;
     A.t = t;
-    if (!p->w_single.empty()) {
-        A.work = p->d_single;
+    if (g.single.count) {
+        A.work = p->d_single + g.single.begin;
         Timed tm(p, "single_step", s);
-        k_single<MODE_STEP, T, T><<<(unsigned)p->w_single.size(), kFftThreads, p->lds_single, s>>>(A, x, imfs, nullptr);
+        k_single<MODE_STEP, T, T><<<(unsigned)g.single.count, kFftThreads, p->lds_single, s>>>(A, x, imfs, nullptr);
     }
-    for (const auto& c : p->chunks) {
-        A.work = p->d_p1 + c.p1_begin;
+    if (g.p1.count) {
+        A.work = p->d_p1 + g.p1.begin;
         {
             Timed tm(p, "pass1_step", s);
-            k_pass1<MODE_STEP, T><<<(unsigned)c.p1_count, kFftThreads, p->lds_p1, s>>>(A, x);
+            k_pass1<MODE_STEP, T><<<(unsigned)g.p1.count, kFftThreads, p->lds_p1, s>>>(A, x);
         }
-        A.work = p->d_p2 + c.p2_begin;
+        A.work = p->d_p2 + g.p2.begin;
         Timed tm(p, "pass2_step", s);
-        k_pass2<MODE_STEP, T, T><<<(unsigned)c.p2_count, kFftThreads, p->lds_p2, s>>>(A, x, imfs, nullptr);
+        k_pass2<MODE_STEP, T, T><<<(unsigned)g.p2.count, kFftThreads, p->lds_p2, s>>>(A, x, imfs, nullptr);
     }
-    if (!p->w_count.empty()) {
+    if (g.count.count) {
         Timed tm(p, "count_resid", s);
-        k_count_resid<<<(unsigned)p->w_count.size(), kFftThreads, 0, s>>>(p->d_sigs, p->d_count, A.resid, A.parts,
-                                                                           A.st);
+        k_count_resid<<<(unsigned)g.count.count, kFftThreads, 0, s>>>(p->d_sigs, p->d_count + g.count.begin, A.resid,
+                                                                       A.parts, A.st);
     }
 }
 
@@ -809,15 +852,15 @@ void launch_final(const fif_plan* p, Bound& b, const T* x, T* rem, int32_t* n_im
         k_single<MODE_REMAINDER, T, T><<<(unsigned)p->w_single.size(), kFftThreads, p->lds_single, s>>>(A, x, nullptr,
                                                                                                        rem);
     }
-    for (const auto& c : p->chunks) {
-        A.work = p->d_p1 + c.p1_begin;
+    if (!p->w_p1.empty()) {
+        A.work = p->d_p1;
         {
             Timed tm(p, "pass1_rem", s);
-            k_pass1<MODE_REMAINDER, T><<<(unsigned)c.p1_count, kFftThreads, p->lds_p1, s>>>(A, x);
+            k_pass1<MODE_REMAINDER, T><<<(unsigned)p->w_p1.size(), kFftThreads, p->lds_p1, s>>>(A, x);
         }
-        A.work = p->d_p2 + c.p2_begin;
+        A.work = p->d_p2;
         Timed tm(p, "pass2_rem", s);
-        k_pass2<MODE_REMAINDER, T, T><<<(unsigned)c.p2_count, kFftThreads, p->lds_p2, s>>>(A, x, nullptr, rem);
+        k_pass2<MODE_REMAINDER, T, T><<<(unsigned)p->w_p2.size(), kFftThreads, p->lds_p2, s>>>(A, x, nullptr, rem);
     }
 }
 
@@ -836,7 +879,33 @@ fif_status batched(fif_plan* p, const T* x, double delta, T* imfs, T* rem, int32
     hipStream_t s = (hipStream_t)stream;
     Bound b = bind(p, ws, delta, info);
     launch_init<T>(p, b, x, s);
-    for (int t = 0; t < p->max_imfs; ++t) launch_step<T>(p, b, t, x, imfs, ws, s);
+    // outer steps: one stream per signal group (forked from and joined back
+    // to the caller's stream); a single group when the proposal network or
+    // feature recording is on (they share buffers across signals) or while
+    // profiling (per-kernel times)
+    const int G = (p->model || p->rec || p->prof) ? 1 : (int)p->groups.size();
+    if (G <= 1) {
+        for (int t = 0; t < p->max_imfs; ++t) launch_step<T>(p, b, t, x, imfs, ws, s, p->all);
+    } else {
+        while ((int)p->gstreams.size() < G - 1) {
+            hipStream_t st = nullptr;
+            HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+            p->gstreams.push_back(st);
+            hipEvent_t ev = nullptr;
+            HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+            p->ev_join.push_back(ev);
+        }
+        if (!p->ev_fork) HIP_TRY(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
+        HIP_TRY(hipEventRecord(p->ev_fork, s));
+        for (int g = 1; g < G; ++g) HIP_TRY(hipStreamWaitEvent(p->gstreams[g - 1], p->ev_fork, 0));
+        for (int t = 0; t < p->max_imfs; ++t)
+            for (int g = 0; g < G; ++g)
+                launch_step<T>(p, b, t, x, imfs, ws, g == 0 ? s : p->gstreams[g - 1], p->groups[g]);
+        for (int g = 1; g < G; ++g) {
+            HIP_TRY(hipEventRecord(p->ev_join[g - 1], p->gstreams[g - 1]));
+            HIP_TRY(hipStreamWaitEvent(s, p->ev_join[g - 1], 0));
+        }
+    }
     launch_final<T>(p, b, x, rem, n_imfs, sig_status, info, s);
     HIP_TRY(hipGetLastError());
     return FIF_OK;
@@ -912,7 +981,7 @@ fif_status single(const T* x, int64_t N, fif_window window, double delta, int32_
     Bound b = bind(p, it->second.ws, delta, info);
     launch_init<T>(p, b, x, s);
     for (int t = 0; t < max_imfs; ++t) {
-        launch_step<T>(p, b, t, x, imfs, it->second.ws, s);
+        launch_step<T>(p, b, t, x, imfs, it->second.ws, s, p->all);
         HIP_TRY(hipMemcpyAsync(hs, b.state, sizeof(SigState), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         if (!hs->active) {

@@ -825,7 +825,9 @@ __global__ __launch_bounds__(kFftThreads) void k_pass2(StepArgs A, const InT* __
     }
     const double2* Y = A.inter + d.inter_off;
     {
-        // e = (t * TR + rl) * TC + s: one TR x TC run per pass-1 tile t
+        // e = (t * TC + s) * TR + rl: consecutive lanes take consecutive
+        // rows of one column, so the LDS stores below are conflict free;
+        // the global reads stay within the TR x TC run of pass-1 tile t
         const int TC = lp.TC;
         const FastDiv ftc = fastdiv(TC);
         const int64_t blk = (int64_t)TC * N2;
@@ -837,8 +839,8 @@ __global__ __launch_bounds__(kFftThreads) void k_pass2(StepArgs A, const InT* __
             yv[q] = make_double2(0.0, 0.0);
             if (e < total) {
                 int s, rl;
-                const int u = fdivmod(e, ftc, s);
-                const int t = fdivmod(u, ftr, rl);
+                const int u = fdivmod(e, ftr, rl);
+                const int t = fdivmod(u, ftc, s);
                 yv[q] = Y[(int64_t)t * blk + (int64_t)(r0 + rl) * TC + s];
             }
         }
@@ -847,8 +849,8 @@ __global__ __launch_bounds__(kFftThreads) void k_pass2(StepArgs A, const InT* __
             const int e = threadIdx.x + q * kFftThreads;
             if (e < total) {
                 int s, rl;
-                const int u = fdivmod(e, ftc, s);
-                const int t = fdivmod(u, ftr, rl);
+                const int u = fdivmod(e, ftr, rl);
+                const int t = fdivmod(u, ftc, s);
                 lds[pass1_col(pr, t, s) * TR + rl] = yv[q];
             }
         }

@@ -23,6 +23,7 @@ struct FeatArgs {
     uint16_t* out;             // proposal slots, indexed by signal
     uint16_t* rec;             // recorded rows [B][max_imfs], or null
     int max_imfs;
+    int s0;                    // first signal (workgroup b handles signal s0 + b)
 };
 
 // Bins are read once, coalesced, in tiles of kFeatTile staged in LDS; each
@@ -42,7 +43,7 @@ __global__ __launch_bounds__(kNetThreads) void k_features(FeatArgs A)
     __shared__ double pw[kFeatTile];
     __shared__ double gs[kNetFeat];
     __shared__ double shd[kNetThreads / 64];
-    const int s = blockIdx.x;
+    const int s = A.s0 + blockIdx.x;
     const SigState* S = A.st + s;
     if (!S->active) return;
     const SigDesc d = A.sigs[s];
