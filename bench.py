@@ -145,6 +145,7 @@ def main():
     ap.add_argument("--cpu-signals", type=int, default=2, help="signals the CPU oracle decomposes")
     ap.add_argument("--cpu-budget", type=float, default=25.0, help="seconds of CPU oracle work at most")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graph", action="store_true", help="time replays of a captured HIP graph (FP32 workloads)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 512 MiB device copy first (a known-size kernel to scale HBM counters by)")
     args = ap.parse_args()
@@ -203,14 +204,17 @@ def main():
         if args.workload == "learned":
             model = fif.Model(path=args.model, max_batch=min(len(lengths), 4096))
             plan.set_proposal(model)
-        for _ in range(args.warmup):
-            plan.run(packed, delta, out=out)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            plan.run(packed, delta, out=out)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
+        use_graph = args.graph
+        stream = torch.cuda.Stream() if use_graph else torch.cuda.current_stream()
+        with torch.cuda.stream(stream):
+            for _ in range(args.warmup):
+                plan.run(packed, delta, out=out, graph=use_graph)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                plan.run(packed, delta, out=out, graph=use_graph)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
         # per-kernel times from separate profiled runs (events around every
         # launch; the signal groups then run one after another)
         prof_steps = max(1, min(args.steps, 2))
@@ -290,6 +294,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": W["workload"], "signals": len(lengths), "samples": total, "delta": delta,
                    "max_imfs": J, "io_dtype": W["io"],
+                   "launch": "hip graph replay" if (args.graph and args.workload != "plain")
+                   else "stream",
                    "form": "plain single-signal" if args.workload == "plain" else
                    ("batched, learned proposal of m" if args.workload == "learned" else "batched")},
     }

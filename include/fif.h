@@ -146,6 +146,26 @@ fif_status fif_decompose_batched_f64(fif_plan* plan, const double* signals, doub
                                      void* workspace, void* stream);
 
 /*
+ * fif_decompose_batched replayed from a HIP graph: the first call captures
+ * every launch of the batched decomposition on `stream` (which must not be
+ * the null stream) into a graph and instantiates it; later calls with the
+ * same arguments, the same proposal model and the same feature buffer
+ * launch that graph with one hipGraphLaunch.  Different arguments replace
+ * the cached graph.  Results equal fif_decompose_batched's.  Not available
+ * while profiling is enabled.
+ */
+fif_status fif_decompose_batched_graph(fif_plan* plan, const float* signals, double delta,
+                                       float* imfs, float* remainders, int32_t* n_imfs,
+                                       fif_imf_info* info, int32_t* sig_status,
+                                       void* workspace, void* stream);
+/* Same with FP64 signals, IMFs and remainders (its own cached graph: a call
+   of the other precision replaces it). */
+fif_status fif_decompose_batched_graph_f64(fif_plan* plan, const double* signals, double delta,
+                                           double* imfs, double* remainders, int32_t* n_imfs,
+                                           fif_imf_info* info, int32_t* sig_status,
+                                           void* workspace, void* stream);
+
+/*
  * Plain single-signal form: one signal of length N, one IMF per host
  * iteration, the host reads the signal's state after every outer step and
  * stops launching once it has finished.  The library allocates and caches

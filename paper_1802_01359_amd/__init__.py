@@ -185,8 +185,11 @@ class Plan:
         check(load().fif_plan_profile_read(self._h, arr, cap, ctypes.byref(n)))
         return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms)) for i in range(min(n.value, cap))}
 
-    def run(self, signals, delta: float, out: BatchResult | None = None, with_info: bool = True) -> BatchResult:
-        """Enqueue the batched decomposition on the current stream (async)."""
+    def run(self, signals, delta: float, out: BatchResult | None = None, with_info: bool = True,
+            graph: bool = False) -> BatchResult:
+        """Enqueue the batched decomposition on the current stream (async);
+        graph=True replays it from a captured HIP graph (not on the null
+        stream)."""
         torch = _torch()
         lib = load()
         if signals.dim() != 1 or signals.numel() != self.total or not signals.is_cuda \
@@ -198,6 +201,9 @@ class Plan:
         base = _ptr(ws)
         aligned = (base + 255) // 256 * 256
         fn = lib.fif_decompose_batched if signals.dtype == torch.float32 else lib.fif_decompose_batched_f64
+        if graph:
+            fn = lib.fif_decompose_batched_graph if signals.dtype == torch.float32 \
+                else lib.fif_decompose_batched_graph_f64
         check(fn(self._h, _ptr(signals), float(delta), _ptr(out.imfs), _ptr(out.remainders), _ptr(out.n_imfs),
                  _ptr(out.info_raw) if with_info else 0, _ptr(out.sig_status), aligned, _stream_ptr(torch)))
         return out

@@ -37,7 +37,8 @@ EXPORTED = (
     "fif_plan_profile", "fif_plan_profile_read",
     "fif_model_create", "fif_model_free", "fif_model_get_params", "fif_model_set_params",
     "fif_model_save", "fif_model_load", "fif_model_forward", "fif_model_grad", "fif_model_train_step",
-    "fif_plan_set_proposal", "fif_plan_record_features",
+    "fif_plan_set_proposal", "fif_plan_record_features", "fif_decompose_batched_graph",
+    "fif_decompose_batched_graph_f64",
 )
 
 NET_FEATURES = 1024
@@ -100,7 +101,8 @@ def load():
     lib.fif_plan_workspace_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
     lib.fif_plan_destroy.restype = ctypes.c_int
     lib.fif_plan_destroy.argtypes = [vp]
-    for name in ("fif_decompose_batched", "fif_decompose_batched_f64"):
+    for name in ("fif_decompose_batched", "fif_decompose_batched_f64", "fif_decompose_batched_graph",
+                 "fif_decompose_batched_graph_f64"):
         f = getattr(lib, name)
         f.restype = ctypes.c_int
         f.argtypes = [vp, vp, dbl, vp, vp, vp, vp, vp, vp, vp]

@@ -118,6 +118,10 @@ struct fif_plan {
     std::vector<hipStream_t> gstreams;   // streams of groups 1..
     hipEvent_t ev_fork = nullptr;
     std::vector<hipEvent_t> ev_join;
+    // graph of the last captured batched call and the arguments it was
+    // captured with
+    hipGraphExec_t gexec = nullptr;
+    std::vector<uintptr_t> gkey;
     size_t lds_single = 0, lds_p1 = 0, lds_p2 = 0;
     // device copies (one allocation)
     DevBuf dmeta, dtabs;
@@ -154,6 +158,7 @@ struct fif_plan {
         for (auto s : gstreams) (void)hipStreamDestroy(s);
         if (ev_fork) (void)hipEventDestroy(ev_fork);
         for (auto e : ev_join) (void)hipEventDestroy(e);
+        if (gexec) (void)hipGraphExecDestroy(gexec);
     }
 };
 
@@ -864,6 +869,22 @@ void launch_final(const fif_plan* p, Bound& b, const T* x, T* rem, int32_t* n_im
     }
 }
 
+// Streams and events of the signal groups (created once per plan).
+fif_status group_streams(fif_plan* p)
+{
+    const int G = (int)p->groups.size();
+    while ((int)p->gstreams.size() < G - 1) {
+        hipStream_t st = nullptr;
+        HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        p->gstreams.push_back(st);
+        hipEvent_t ev = nullptr;
+        HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        p->ev_join.push_back(ev);
+    }
+    if (!p->ev_fork) HIP_TRY(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
+    return FIF_OK;
+}
+
 template <typename T>
 fif_status batched(fif_plan* p, const T* x, double delta, T* imfs, T* rem, int32_t* n_imfs, fif_imf_info* info,
                    int32_t* sig_status, void* ws, void* stream)
@@ -887,15 +908,8 @@ fif_status batched(fif_plan* p, const T* x, double delta, T* imfs, T* rem, int32
     if (G <= 1) {
         for (int t = 0; t < p->max_imfs; ++t) launch_step<T>(p, b, t, x, imfs, ws, s, p->all);
     } else {
-        while ((int)p->gstreams.size() < G - 1) {
-            hipStream_t st = nullptr;
-            HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-            p->gstreams.push_back(st);
-            hipEvent_t ev = nullptr;
-            HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-            p->ev_join.push_back(ev);
-        }
-        if (!p->ev_fork) HIP_TRY(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
+        fif_status gs = group_streams(p);
+        if (gs != FIF_OK) return gs;
         HIP_TRY(hipEventRecord(p->ev_fork, s));
         for (int g = 1; g < G; ++g) HIP_TRY(hipStreamWaitEvent(p->gstreams[g - 1], p->ev_fork, 0));
         for (int t = 0; t < p->max_imfs; ++t)
@@ -999,6 +1013,51 @@ fif_status single(const T* x, int64_t N, fif_window window, double delta, int32_
     return FIF_OK;
 }
 
+// Capture-once, replay-many form of batched().
+template <typename T>
+fif_status batched_graph(fif_plan* plan, const T* signals, double delta, T* imfs, T* remainders, int32_t* n_imfs, fif_imf_info* info, int32_t* sig_status,
+                                       void* workspace, void* stream)
+{
+    g_err.clear();
+    if (!plan) return fail(FIF_ERR_INVALID_ARG, "plan is null");
+    if (!stream) return fail(FIF_ERR_INVALID_ARG, "graph replay needs a non-null stream");
+    if (plan->prof) return fail(FIF_ERR_INVALID_ARG, "graph replay is not available while profiling");
+    uint64_t dbits;
+    std::memcpy(&dbits, &delta, sizeof(dbits));
+    const std::vector<uintptr_t> key = {(uintptr_t)signals, (uintptr_t)dbits,       (uintptr_t)imfs,
+                                        (uintptr_t)remainders, (uintptr_t)n_imfs, (uintptr_t)info,
+                                        (uintptr_t)sig_status, (uintptr_t)workspace, (uintptr_t)plan->model,
+                                        (uintptr_t)plan->rec, (uintptr_t)sizeof(T)};
+    hipStream_t s = (hipStream_t)stream;
+    if (!plan->gexec || key != plan->gkey) {
+        if (plan->gexec) {
+            HIP_TRY(hipGraphExecDestroy(plan->gexec));
+            plan->gexec = nullptr;
+        }
+        const fif_status gs = group_streams(plan);   // not inside the capture
+        if (gs != FIF_OK) return gs;
+        HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        const fif_status st = batched<T>(plan, signals, delta, imfs, remainders, n_imfs, info, sig_status,
+                                             workspace, stream);
+        hipGraph_t graph = nullptr;
+        const hipError_t ec = hipStreamEndCapture(s, &graph);
+        if (st != FIF_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (ec != hipSuccess) return fail(FIF_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(ec));
+        const hipError_t ei = hipGraphInstantiate(&plan->gexec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) {
+            plan->gexec = nullptr;
+            return fail(FIF_ERR_DEVICE, "graph instantiation failed: %s", hipGetErrorString(ei));
+        }
+        plan->gkey = key;
+    }
+    HIP_TRY(hipGraphLaunch(plan->gexec, s));
+    return FIF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1015,6 +1074,20 @@ fif_status fif_decompose_batched_f64(fif_plan* plan, const double* signals, doub
                                      void* workspace, void* stream)
 {
     return batched<double>(plan, signals, delta, imfs, remainders, n_imfs, info, sig_status, workspace, stream);
+}
+
+fif_status fif_decompose_batched_graph(fif_plan* plan, const float* signals, double delta, float* imfs,
+                                       float* remainders, int32_t* n_imfs, fif_imf_info* info, int32_t* sig_status,
+                                       void* workspace, void* stream)
+{
+    return batched_graph<float>(plan, signals, delta, imfs, remainders, n_imfs, info, sig_status, workspace, stream);
+}
+
+fif_status fif_decompose_batched_graph_f64(fif_plan* plan, const double* signals, double delta, double* imfs,
+                                           double* remainders, int32_t* n_imfs, fif_imf_info* info,
+                                           int32_t* sig_status, void* workspace, void* stream)
+{
+    return batched_graph<double>(plan, signals, delta, imfs, remainders, n_imfs, info, sig_status, workspace, stream);
 }
 
 fif_status fif_decompose(const float* signal, int64_t N, fif_window window, double delta, int32_t max_imfs,

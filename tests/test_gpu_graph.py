@@ -1,0 +1,84 @@
+"""Batched decomposition replayed from a captured HIP graph, through the C ABI.
+
+Every replay must equal the eager fif_decompose_batched result bitwise.
+Replays are separated by other eager GPU work and synchronisations, and a
+second argument set forces a new capture.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import siggen
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1802_01359_amd as fif  # noqa: E402
+
+
+def _same(a, b):
+    return (torch.equal(a.imfs, b.imfs) and torch.equal(a.remainders, b.remainders)
+            and torch.equal(a.n_imfs, b.n_imfs) and torch.equal(a.info_raw, b.info_raw)
+            and torch.equal(a.sig_status, b.sig_status))
+
+
+def test_graph_replays_equal_eager_runs():
+    lengths = [65536] * 4 + [4096, 1000, 131072, 30, 8192]
+    sig = [siggen.chirps(i) if n == 65536 else siggen.uneven_signal(i, n) for i, n in enumerate(lengths)]
+    print("graph lengths %s" % lengths, flush=True)
+    x = torch.tensor(np.concatenate(sig), dtype=torch.float32).cuda()
+    plan = fif.Plan(lengths, 10)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ref = plan.run(x, 1e-3)
+        stream.synchronize()
+        other = fif.Plan([4096, 2048], 4)
+        ox = torch.tensor(np.concatenate([siggen.uneven_signal(50, 4096), siggen.uneven_signal(51, 2048)]),
+                          dtype=torch.float32).cuda()
+        out = plan.alloc_outputs(torch.float32)
+        for rep in range(3):
+            out.imfs.fill_(7.0)
+            plan.run(x, 1e-3, out=out, graph=True)
+            stream.synchronize()
+            assert _same(out, ref), "replay %d" % rep
+            other.run(ox, 1e-3)                 # eager work between replays
+            _ = (x * 2.0).sum().item()
+            stream.synchronize()
+        # new arguments: another delta and other output buffers
+        ref2 = plan.run(x, 1e-4)
+        stream.synchronize()
+        out2 = plan.alloc_outputs(torch.float32)
+        for rep in range(2):
+            plan.run(x, 1e-4, out=out2, graph=True)
+            stream.synchronize()
+            assert _same(out2, ref2), "second capture replay %d" % rep
+
+
+def test_graph_rejects_the_null_stream():
+    plan = fif.Plan([4096], 2)
+    x = torch.tensor(siggen.uneven_signal(3, 4096), dtype=torch.float32).cuda()
+    with pytest.raises(fif.FifError):
+        with torch.cuda.stream(torch.cuda.default_stream()):
+            plan.run(x, 1e-3, graph=True)
+
+
+def test_graph_replays_fp64():
+    lengths = [4096, 2048, 65536]
+    sig = [siggen.tones3(), siggen.uneven_signal(7, 2048), siggen.chirps(3)]
+    print("graph fp64 lengths %s" % lengths, flush=True)
+    x = torch.tensor(np.concatenate(sig), dtype=torch.float64).cuda()
+    plan = fif.Plan(lengths, 8)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ref = plan.run(x, 1e-3)
+        stream.synchronize()
+        out = plan.alloc_outputs(torch.float64)
+        for rep in range(3):
+            plan.run(x, 1e-3, out=out, graph=True)
+            stream.synchronize()
+            assert _same(out, ref), "replay %d" % rep
+            _ = (x * 3.0).sum().item()
