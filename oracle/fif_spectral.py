@@ -13,6 +13,20 @@ spectrum by Parseval's identity (the step used in the proof of Theorem 2).
 Everything else (extrema count, mask length, rounding floor, window column)
 follows the same readings as the time-domain oracle and reuses its helpers.
 numpy's FFT is the only library primitive.
+
+Variants beyond the plain method (each off by default):
+  - stop="abs": the absolute criterion of equation "Discrete_Abs_StopCond",
+    ||s_{m+1} - s_m||_2 < delta, IMF = s_m (m >= 1, the smallest such m);
+  - stop="apriori": m = N0, the smallest N0 >= 1 satisfying inequality
+    "N0_discrete" of Theorem 5, no scan at all (the a-priori estimate the
+    paper's Section 4 mentions before the SD scan);
+  - gamma > 0: the thresholded IMF of equation "IMF_cont_stop_threshold",
+    discretised: a bin whose factor (1 - lambda_j)^m is >= 1 - gamma is taken
+    whole (lambda_j replaced by 0);
+  - mask_rule=2: the spectral-peak mask length of Section 2 ("highest
+    frequency peak" of the spectrum), read as L = ceil(N / f), f the highest
+    bin 1 <= f <= N/2 whose power is >= peak_rho times the strongest
+    non-constant bin's (a pure tone at f cycles then gets the L of rule 0).
 """
 from __future__ import annotations
 
@@ -29,8 +43,50 @@ def eigenvalues(N: int, L: int) -> np.ndarray:
     return np.fft.fft(c).real
 
 
+def zero_eigenvalues(N: int, L: int) -> int:
+    """k of Theorem 5: eigenvalues lambda_p (p = 1..N-1) that are exactly 0,
+    i.e. sin(pi L p / N) = 0, i.e. N divides L*p."""
+    return sum(1 for p in range(1, N) if (L * p) % N == 0)
+
+
+def apriori_n0(R, N: int, L: int, delta: float) -> int:
+    """Smallest N0 >= 1 with N0^N0 / (N0+1)^(N0+1) < delta / (||U^T r||_inf
+    sqrt(N - 1 - k)) (Theorem 5), compared in logarithms; R = DFT(r)."""
+    st_inf = float(np.max(np.abs(R))) / math.sqrt(N)   # unitary DFT coefficients
+    rest = N - 1 - zero_eigenvalues(N, L)
+    if st_inf == 0.0 or rest <= 0:
+        return 1
+    rhs = math.log(delta / (st_inf * math.sqrt(rest)))
+
+    def lhs(n):
+        return n * math.log(n) - (n + 1) * math.log(n + 1)
+    hi = 1
+    while lhs(hi) >= rhs:
+        hi *= 2
+    lo = hi // 2   # lhs(lo) >= rhs unless lo == 0
+    if lo == 0:
+        return 1
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        if lhs(mid) < rhs:
+            hi = mid
+        else:
+            lo = mid
+    return hi
+
+
+def peak_frequency(R, rho: float) -> int:
+    """Highest bin f in [1, N/2] with |R_f|^2 >= rho * max_{1<=j<=N/2} |R_j|^2."""
+    N = R.size
+    P = np.abs(R[1:N // 2 + 1]) ** 2
+    top = float(P.max()) if P.size else 0.0
+    idx = np.flatnonzero(P >= rho * top)
+    return int(idx[-1]) + 1 if idx.size and top > 0 else 1
+
+
 def decompose(s, delta: float, max_imfs: int, *, mask_rule: int = 0, nu: float = 1.6,
-              max_inner: int = 1_000_000, floor_tau: float = 1e-9) -> dif.Decomposition:
+              max_inner: int = 1_000_000, floor_tau: float = 1e-9, stop: str = "sd",
+              gamma: float = 0.0, peak_rho: float = 0.1) -> dif.Decomposition:
     s = np.ascontiguousarray(np.asarray(s, dtype=np.float64))
     N = s.size
     r = s.copy()
@@ -49,31 +105,61 @@ def decompose(s, delta: float, max_imfs: int, *, mask_rule: int = 0, nu: float =
         if k < 2:
             reason = dif.STOP_FEW_EXTREMA
             break
-        L = dif.mask_length(N, k, mask_rule, nu)
-        lam = eigenvalues(N, L)
         R = np.fft.fft(r)
+        if mask_rule == 2:
+            L = max(1, -(-N // peak_frequency(R, peak_rho)))
+        else:
+            L = dif.mask_length(N, k, mask_rule, nu)
+        lam = eigenvalues(N, L)
         P = (R.real * R.real + R.imag * R.imag)
         mu = (1.0 - lam) ** 2
         lam2 = lam * lam
-        # N0 = 1, 2, ...: SD_{N0} = ||(1-lam)^{N0-1} lam R|| / ||(1-lam)^{N0-1} R||
-        x = P.copy()
-        m = 0
-        sd = 0.0
-        sd_prev = math.inf
         flags = 0
-        while True:
-            m += 1
-            num = float(np.sum(x * lam2))
-            den = float(np.sum(x))
-            sd_prev = sd if m > 1 else math.inf
-            sd = math.sqrt(num / den) if den > 0 else 0.0
-            if sd <= delta:
-                break
-            if m >= max_inner:
+        if stop == "sd":
+            # N0 = 1, 2, ...: SD_{N0} = ||(1-lam)^{N0-1} lam R|| / ||(1-lam)^{N0-1} R||
+            x = P.copy()
+            m = 0
+            sd = 0.0
+            sd_prev = math.inf
+            while True:
+                m += 1
+                num = float(np.sum(x * lam2))
+                den = float(np.sum(x))
+                sd_prev = sd if m > 1 else math.inf
+                sd = math.sqrt(num / den) if den > 0 else 0.0
+                if sd <= delta:
+                    break
+                if m >= max_inner:
+                    flags |= dif.FLAG_CAP
+                    break
+                x = x * mu
+        elif stop == "abs":
+            # ||s_{m+1} - s_m||_2 = ||W s_m||_2 = sqrt(sum |R|^2 lam^2 mu^m / N) (Parseval)
+            x = P * mu
+            m = 0
+            sd = math.sqrt(float(np.sum(P * lam2)) / N)   # m = 0
+            while True:
+                m += 1
+                sd_prev = sd
+                sd = math.sqrt(float(np.sum(x * lam2)) / N)
+                if sd < delta:
+                    break
+                if m >= max_inner:
+                    flags |= dif.FLAG_CAP
+                    break
+                x = x * mu
+        elif stop == "apriori":
+            m = apriori_n0(R, N, L, delta)
+            if m > max_inner:
+                m = max_inner
                 flags |= dif.FLAG_CAP
-                break
-            x = x * mu
+            sd = math.sqrt(float(np.sum(P * lam2 * mu ** m)) / N)
+            sd_prev = math.sqrt(float(np.sum(P * lam2 * mu ** (m - 1))) / N)
+        else:
+            raise ValueError(stop)
         g = np.power(1.0 - lam, m)
+        if gamma > 0.0:
+            g = np.where(g >= 1.0 - gamma, 1.0, g)
         imf = np.fft.ifft(g * R).real
         imfs.append(imf)
         r = r - imf

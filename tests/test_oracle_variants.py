@@ -1,0 +1,153 @@
+"""Pins of the spectral oracle's variants: the absolute stop criterion, the
+a-priori N0 of Theorem 5, the thresholded IMF and the spectral-peak mask
+length.  Each is checked against the time-domain iteration, a closed form
+on pure tones, or a bound the paper proves.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+import siggen
+from oracle import dif
+from oracle import fif_spectral as fs
+
+
+def _tone(N, k0, amp=1.0, phase=0.3):
+    i = np.arange(N)
+    return amp * np.cos(2 * np.pi * k0 * i / N + phase)
+
+
+# ------------------------------------------------------- absolute criterion --
+
+@pytest.mark.parametrize("delta", [1e-1, 1e-2, 3e-3])
+def test_absolute_stop_matches_time_domain_iteration(delta):
+    """m = smallest m >= 1 with ||s_{m+1} - s_m||_2 < delta, the step norms
+    taken from the literal time-domain iteration."""
+    N = 256
+    s = siggen.tones3(N=N, freqs=(3.0, 11.0, 40.0))
+    d = fs.decompose(s, delta, 1, stop="abs")
+    L = d.L[0]
+    _, _, step = dif.inner_trace(s, L, 3000, 1)
+    # step[m] = ||s_{m+1} - s_m||, m counted from 0
+    m_td = next(m for m in range(1, step.size) if step[m] < delta)
+    assert d.m[0] == m_td
+    assert d.sd[0] == pytest.approx(step[m_td], rel=1e-10)
+    assert d.sd_prev[0] == pytest.approx(step[m_td - 1], rel=1e-10)
+
+
+def test_absolute_stop_on_a_pure_tone():
+    """||W s_m|| = lambda (1 - lambda)^m ||s|| for an eigenvector."""
+    N, k0 = 1024, 37
+    s = _tone(N, k0)
+    delta = 1e-2
+    d = fs.decompose(s, delta, 1, stop="abs")
+    L = d.L[0]
+    lam = float(np.sin(np.pi * L * k0 / N) / (L * np.sin(np.pi * k0 / N))) ** 4
+    ns = float(np.linalg.norm(s))
+    m = 1
+    while lam * (1 - lam) ** m * ns >= delta:
+        m += 1
+    assert d.m[0] == m
+
+
+# ---------------------------------------------------------- a-priori N0 --
+
+def test_zero_eigenvalue_count():
+    for N, L in ((128, 6), (120, 40), (64, 64), (210, 35), (97, 5)):
+        lam = fs.eigenvalues(N, L)
+        assert fs.zero_eigenvalues(N, L) == math.gcd(L, N) - 1
+        assert fs.zero_eigenvalues(N, L) == int(np.sum(np.abs(lam[1:]) < 1e-12))
+
+
+@pytest.mark.parametrize("delta", [1.0, 0.3, 0.1])
+def test_apriori_n0_satisfies_theorem5(delta):
+    """Theorem 5: for m >= N0, ||s_{m+1} - s_m|| < delta; so the a-priori
+    count is never below the absolute criterion's."""
+    N = 128
+    s = siggen.tones3(N=N, freqs=(3.0, 11.0, 30.0))
+    d = fs.decompose(s, delta, 1, stop="apriori")
+    n0, L = d.m[0], d.L[0]
+    _, _, step = dif.inner_trace(s, L, n0 + 40, 1)
+    assert np.all(step[n0:] < delta)
+    da = fs.decompose(s, delta, 1, stop="abs")
+    assert da.L[0] == L and da.m[0] <= n0
+
+
+def test_apriori_n0_is_minimal():
+    """N0 - 1 does not satisfy the inequality (evaluated here with exact
+    rationals, independently of the oracle's logarithms)."""
+    from fractions import Fraction
+    N = 64
+    s = siggen.tones3(N=N, freqs=(2.0, 5.0, 13.0))
+    R = np.fft.fft(s)
+    for L in (4, 7, 12):
+        for delta in (2.0, 0.5):
+            n0 = fs.apriori_n0(R, N, L, delta)
+            rest = N - 1 - (math.gcd(L, N) - 1)
+            bound = delta / (float(np.max(np.abs(R))) / math.sqrt(N) * math.sqrt(rest))
+            b = Fraction(bound)
+
+            def holds(n):
+                return Fraction(n ** n, (n + 1) ** (n + 1)) < b
+            assert holds(n0)
+            assert n0 == 1 or not holds(n0 - 1)
+
+
+# ------------------------------------------------------ thresholded IMF --
+
+def test_threshold_vanishing_gamma_is_the_plain_imf():
+    s = siggen.tones3()
+    a = fs.decompose(s, 1e-3, 5)
+    b = fs.decompose(s, 1e-3, 5, gamma=1e-300)
+    assert (a.k, a.L, a.m) == (b.k, b.L, b.m)
+    assert np.array_equal(a.imfs, b.imfs)
+
+
+@pytest.mark.parametrize("gamma", [1e-1, 1e-2, 1e-3])
+def test_threshold_bound(gamma):
+    """Discrete form of the bound behind the thresholding proposition:
+    the IMF changes only on thresholded bins, by a factor 1 - (1-lambda)^m
+    <= gamma there, so ||IMF^SC - IMF^TH||_2 <= gamma ||r||_2."""
+    s = siggen.tones3()
+    a = fs.decompose(s, 1e-3, 1)
+    b = fs.decompose(s, 1e-3, 1, gamma=gamma)
+    assert (a.k, a.L, a.m) == (b.k, b.L, b.m)
+    assert np.linalg.norm(a.imfs[0] - b.imfs[0]) <= gamma * np.linalg.norm(s) * (1 + 1e-12)
+
+
+def test_threshold_takes_a_slowly_decaying_tone_whole():
+    N, k0 = 1024, 3
+    s = _tone(N, k0) + 1e-3 * _tone(N, 200)
+    d = fs.decompose(s, 1e-3, 1, gamma=0.5)
+    L, m = d.L[0], d.m[0]
+    lam = float(np.sin(np.pi * L * k0 / N) / (L * np.sin(np.pi * k0 / N))) ** 4
+    g = (1 - lam) ** m
+    expected = 1.0 if g >= 0.5 else g
+    # the IMF's component at k0 is the tone scaled by the (thresholded) factor
+    comp = np.fft.fft(d.imfs[0])[k0] / np.fft.fft(_tone(N, k0))[k0]
+    assert abs(comp - expected) < 1e-12
+
+
+# ------------------------------------------------ spectral-peak mask rule --
+
+@pytest.mark.parametrize("N,f", [(1024, 37), (4096, 200), (1000, 3)])
+def test_peak_rule_on_a_pure_tone_equals_count_rule(N, f):
+    s = _tone(N, f)
+    a = fs.decompose(s, 1e-3, 1)
+    b = fs.decompose(s, 1e-3, 1, mask_rule=2)
+    assert b.L[0] == -(-N // f)
+    # the count rule sees 2f or 2f - 1 extrema (endpoints are not extrema)
+    assert a.L[0] in (-(-2 * N // (2 * f)), -(-2 * N // (2 * f - 1)))
+
+
+def test_peak_rule_picks_the_highest_significant_peak():
+    N = 2048
+    for a2, rho, f_exp in ((0.5, 0.1, 300), (0.2, 0.1, 40), (0.2, 0.01, 300)):
+        s = _tone(N, 40) + a2 * _tone(N, 300)
+        R = np.fft.fft(s)
+        assert fs.peak_frequency(R, rho) == f_exp
+        d = fs.decompose(s, 1e-3, 1, mask_rule=2, peak_rho=rho)
+        assert d.L[0] == -(-N // f_exp)
