@@ -87,19 +87,35 @@ typedef enum {
 #define FIF_STOP_FAILED 3
 
 typedef struct {
-    int32_t mask_rule;   /* 0: L = ceil(2N/k)  1: L = 2*floor(nu*N/k) */
-    int32_t reserved0;
+    int32_t mask_rule;   /* 0: L = ceil(2N/k)  1: L = 2*floor(nu*N/k) (equation
+                            "Unif_Mask_length")  2: L = ceil(N/f), f the highest
+                            bin 1 <= f <= N/2 whose power is >= peak_rho times
+                            the strongest of those bins (the spectral-peak rule
+                            of Section 2) */
+    int32_t stop_mode;   /* 0: smallest m with SD_m <= delta (equation "SD")
+                            1: smallest m >= 1 with ||s_{m+1} - s_m||_2 < delta
+                               (equation "Discrete_Abs_StopCond"), IMF = s_m
+                            2: m = N0, the smallest N0 >= 1 satisfying
+                               inequality "N0_discrete" of Theorem 5 (no search)
+                            modes 1 and 2 need every length <= 65536 */
     double nu;           /* mask_rule 1 constant, default 1.6 */
     int64_t max_inner;   /* cap on m, default 1000000 */
     double floor_tau;    /* rounding floor, default 1e-9 */
+    double gamma;        /* > 0: thresholded IMF (equation
+                            "IMF_cont_stop_threshold"): bins with
+                            (1 - lambda)^m >= 1 - gamma go whole into the IMF;
+                            0 (default): off; must be < 1 */
+    double peak_rho;     /* mask_rule 2 fraction, in (0, 1], default 0.1 */
 } fif_options;
 
 typedef struct {
     int64_t k;           /* extrema count of the residual the IMF came from */
     int64_t L;           /* half-support of the triangle */
     int64_t m;           /* inner step count */
-    double sd;           /* SD_m (FP64, Parseval) */
-    double sd_prev;      /* SD_{m-1}; +inf when m == 1 */
+    double sd;           /* SD_m (FP64, Parseval); stop modes 1 and 2:
+                            ||s_{m+1} - s_m||_2 */
+    double sd_prev;      /* SD_{m-1}, +inf when m == 1; stop modes 1 and 2:
+                            ||s_m - s_{m-1}||_2 */
     uint32_t flags;      /* FIF_IMF_* */
     uint32_t evals;      /* low 16 bits: FP32 passes over the spectrum in the
                             search for m; high 16 bits: FP64 evaluations */

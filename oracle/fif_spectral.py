@@ -43,6 +43,34 @@ def eigenvalues(N: int, L: int) -> np.ndarray:
     return np.fft.fft(c).real
 
 
+def eigenvalues_closed(N: int, L: int) -> np.ndarray:
+    """lambda_p, p = 0..N-1, from the closed form of equation "eig2":
+    [sin(pi L p / N) / (L sin(pi p / N))]^4, lambda_0 = 1, with L p reduced
+    modulo N exactly and folded to min(t, N - t) (the fourth power hides the
+    sign) so that every sine argument is at most pi/2: relative, not
+    absolute, rounding error, which matters once m ~ 1e5 multiplies it."""
+    p = np.arange(N, dtype=np.int64)
+    t = ((L % N) * p) % N
+    t = np.minimum(t, N - t)
+    u = np.minimum(p, N - p)
+    lam = np.ones(N)
+    nz = p != 0
+    q = np.sin(np.pi * t[nz] / N) / (L * np.sin(np.pi * u[nz] / N))
+    lam[nz] = q ** 4
+    return lam
+
+
+def _pow1m(lam, e):
+    """(1 - lambda)^e as exp(e log1p(-lambda)): the factor of equation
+    "IMF1_direct" without rounding 1 - lambda first (whose relative error
+    would grow e-fold); lambda is clamped to [0, 1], where it lies (a fourth
+    power, at most 1), so FFT rounding cannot push a factor above 1."""
+    lam = np.clip(lam, 0.0, 1.0)
+    with np.errstate(divide="ignore"):
+        lg = np.log1p(-lam)
+    return np.exp(e * lg) if e > 0 else np.ones_like(lam)
+
+
 def zero_eigenvalues(N: int, L: int) -> int:
     """k of Theorem 5: eigenvalues lambda_p (p = 1..N-1) that are exactly 0,
     i.e. sin(pi L p / N) = 0, i.e. N divides L*p."""
@@ -110,7 +138,7 @@ def decompose(s, delta: float, max_imfs: int, *, mask_rule: int = 0, nu: float =
             L = max(1, -(-N // peak_frequency(R, peak_rho)))
         else:
             L = dif.mask_length(N, k, mask_rule, nu)
-        lam = eigenvalues(N, L)
+        lam = eigenvalues_closed(N, L)
         P = (R.real * R.real + R.imag * R.imag)
         mu = (1.0 - lam) ** 2
         lam2 = lam * lam
@@ -153,11 +181,11 @@ def decompose(s, delta: float, max_imfs: int, *, mask_rule: int = 0, nu: float =
             if m > max_inner:
                 m = max_inner
                 flags |= dif.FLAG_CAP
-            sd = math.sqrt(float(np.sum(P * lam2 * mu ** m)) / N)
-            sd_prev = math.sqrt(float(np.sum(P * lam2 * mu ** (m - 1))) / N)
+            sd = math.sqrt(float(np.sum(P * lam2 * _pow1m(lam, 2 * m))) / N)
+            sd_prev = math.sqrt(float(np.sum(P * lam2 * _pow1m(lam, 2 * (m - 1)))) / N)
         else:
             raise ValueError(stop)
-        g = np.power(1.0 - lam, m)
+        g = _pow1m(lam, m)
         if gamma > 0.0:
             g = np.where(g >= 1.0 - gamma, 1.0, g)
         imf = np.fft.ifft(g * R).real

@@ -53,8 +53,9 @@ class FifError(RuntimeError):
 
 
 class _Options(ctypes.Structure):
-    _fields_ = [("mask_rule", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("nu", ctypes.c_double),
-                ("max_inner", ctypes.c_int64), ("floor_tau", ctypes.c_double)]
+    _fields_ = [("mask_rule", ctypes.c_int32), ("stop_mode", ctypes.c_int32), ("nu", ctypes.c_double),
+                ("max_inner", ctypes.c_int64), ("floor_tau", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("peak_rho", ctypes.c_double)]
 
 
 class KernelTime(ctypes.Structure):
@@ -68,13 +69,17 @@ assert IMF_INFO_DTYPE.itemsize == 48
 
 @dataclass
 class Options:
-    mask_rule: int = 0
+    mask_rule: int = 0          # 0 ceil(2N/k), 1 2*floor(nu*N/k), 2 spectral peak
     nu: float = 1.6
     max_inner: int = 1_000_000
     floor_tau: float = 1e-9
+    stop_mode: int = 0          # 0 SD <= delta, 1 ||s_{m+1}-s_m|| < delta, 2 a-priori N0
+    gamma: float = 0.0          # > 0: thresholded IMF
+    peak_rho: float = 0.1
 
     def c(self) -> _Options:
-        return _Options(self.mask_rule, 0, self.nu, self.max_inner, self.floor_tau)
+        return _Options(self.mask_rule, self.stop_mode, self.nu, self.max_inner, self.floor_tau, self.gamma,
+                        self.peak_rho)
 
 
 _lib = None

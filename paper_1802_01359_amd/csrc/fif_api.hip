@@ -192,8 +192,12 @@ fif_status set_lds_limits()
         set((const void*)k_pass2<MODE_FORWARD, double, double>);
         set((const void*)k_pass2<MODE_STEP, double, double>);
         set((const void*)k_pass2<MODE_REMAINDER, double, double>);
-        set((const void*)k_scan<kScanBinsPerThread, false>);
-        set((const void*)k_scan<kScanBinsPerThread, true>);
+        set((const void*)k_scan<kScanBinsPerThread, false, 0>);
+        set((const void*)k_scan<kScanBinsPerThread, true, 0>);
+        set((const void*)k_scan<kScanBinsPerThread, false, 1>);
+        set((const void*)k_scan<kScanBinsPerThread, true, 1>);
+        set((const void*)k_scan<kScanBinsPerThread, false, 2>);
+        set((const void*)k_scan<kScanBinsPerThread, true, 2>);
     });
     if (err != hipSuccess) return fail(FIF_ERR_DEVICE, "hipFuncSetAttribute: %s", hipGetErrorString(err));
     return FIF_OK;
@@ -201,7 +205,11 @@ fif_status set_lds_limits()
 
 fif_status validate_opts(const fif_options& o)
 {
-    if (o.mask_rule != 0 && o.mask_rule != 1) return fail(FIF_ERR_INVALID_ARG, "mask_rule must be 0 or 1");
+    if (o.mask_rule < 0 || o.mask_rule > 2) return fail(FIF_ERR_INVALID_ARG, "mask_rule must be 0, 1 or 2");
+    if (o.stop_mode < 0 || o.stop_mode > 2) return fail(FIF_ERR_INVALID_ARG, "stop_mode must be 0, 1 or 2");
+    if (!(o.gamma >= 0.0 && o.gamma < 1.0)) return fail(FIF_ERR_INVALID_ARG, "gamma must be in [0, 1)");
+    if (o.mask_rule == 2 && !(o.peak_rho > 0.0 && o.peak_rho <= 1.0))
+        return fail(FIF_ERR_INVALID_ARG, "peak_rho must be in (0, 1]");
     if (o.mask_rule == 1 && !(o.nu > 0.0 && std::isfinite(o.nu)))
         return fail(FIF_ERR_INVALID_ARG, "nu must be positive and finite");
     if (o.max_inner < 1 || o.max_inner > (int64_t)1 << 40)
@@ -273,10 +281,12 @@ void fif_options_default(fif_options* opt)
 {
     if (!opt) return;
     opt->mask_rule = 0;
-    opt->reserved0 = 0;
+    opt->stop_mode = 0;
     opt->nu = 1.6;
     opt->max_inner = 1000000;
     opt->floor_tau = 1e-9;
+    opt->gamma = 0.0;
+    opt->peak_rho = 0.1;
 }
 
 const char* fif_last_error(void) { return g_err.c_str(); }
@@ -323,6 +333,9 @@ fif_status fif_plan_create(fif_plan** out, const int64_t* lengths, int32_t B, in
         if (!smooth7(N))
             return fail(FIF_ERR_UNSUPPORTED_LENGTH, "signal %d: length %lld has a prime factor > 7", b,
                         (long long)N);
+        if (opt.stop_mode != 0 && N / 2 > (int64_t)kScanBinsPerThread * kScanThreads)
+            return fail(FIF_ERR_INVALID_ARG, "signal %d: stop_mode %d supports lengths up to %d", b, opt.stop_mode,
+                        2 * kScanBinsPerThread * kScanThreads);
         if (!len_id.count(N)) {
             LenPlan lp;
             st = plan_length(N, lp);
@@ -663,6 +676,7 @@ Bound bind(const fif_plan* p, void* ws, double delta, fif_imf_info* info)
     A.dtab = p->d_dtab;
     A.ctab = p->d_ctab;
     A.itab = p->d_itab;
+    A.gamma = p->opt.gamma;
     A.spec0 = (double2*)(w + p->ws_spec0);
     A.spec1 = (double2*)(w + p->ws_spec1);
     A.inter = (double2*)(w + p->ws_inter);
@@ -693,6 +707,7 @@ Bound bind(const fif_plan* p, void* ws, double delta, fif_imf_info* info)
     S.nu = p->opt.nu;
     S.max_inner = p->opt.max_inner;
     S.floor_tau = p->opt.floor_tau;
+    S.stop_mode = p->opt.stop_mode;
     return b;
 }
 
@@ -727,6 +742,17 @@ void launch_init(const fif_plan* p, Bound& b, const T* x, hipStream_t s)
     }
 }
 
+template <bool PRE>
+void launch_k_scan(int mode, int n, size_t lds, hipStream_t s, const ScanArgs& S)
+{
+    if (mode == 1)
+        k_scan<kScanBinsPerThread, PRE, 1><<<(unsigned)n, kScanThreads, lds, s>>>(S);
+    else if (mode == 2)
+        k_scan<kScanBinsPerThread, PRE, 2><<<(unsigned)n, kScanThreads, lds, s>>>(S);
+    else
+        k_scan<kScanBinsPerThread, PRE, 0><<<(unsigned)n, kScanThreads, lds, s>>>(S);
+}
+
 // Search for m of every active signal.  With a proposal model or feature
 // recording the step starts (count combine, stop rules, L) run first, then
 // the features, the network and the proposals, then the searches.
@@ -738,11 +764,15 @@ void launch_scan(const fif_plan* p, Bound& b, int t, void* ws, hipStream_t s, co
     const unsigned nb = (unsigned)g.sbig.count, nt = (unsigned)g.btile.count;
     const Work* btile = p->d_btile + g.btile.begin;
     const size_t scan_lds = sizeof(float) * kScanBinsPerThread * kScanThreads;
+    if (p->opt.mask_rule == 2) {
+        Timed tm(p, "peak", s);
+        k_peak<<<(unsigned)(g.s1 - g.s0), 256, 0, s>>>(S, g.s0, p->opt.peak_rho);
+    }
     if (!split) {
         if (g.ssmall.count) {
             S.list = p->d_scan_small + g.ssmall.begin;
             Timed tm(p, "scan", s);
-            k_scan<kScanBinsPerThread, false><<<(unsigned)g.ssmall.count, kScanThreads, scan_lds, s>>>(S);
+            launch_k_scan<false>(p->opt.stop_mode, g.ssmall.count, scan_lds, s, S);
         }
         if (nb) {
             Timed tm(p, "scan_big", s);
@@ -793,7 +823,7 @@ void launch_scan(const fif_plan* p, Bound& b, int t, void* ws, hipStream_t s, co
         if (g.ssmall.count) {
             S.list = p->d_scan_small + g.ssmall.begin;
             Timed tm(p, "scan", s);
-            k_scan<kScanBinsPerThread, true><<<(unsigned)g.ssmall.count, kScanThreads, scan_lds, s>>>(S);
+            launch_k_scan<true>(p->opt.stop_mode, g.ssmall.count, scan_lds, s, S);
         }
         if (nb && p->model) {
             S.list = p->d_scan_big + g.sbig.begin;
@@ -934,7 +964,7 @@ struct SingleCache {
         void* ws = nullptr;
         SigState* host_state = nullptr;
     };
-    std::map<std::tuple<int, int64_t, int32_t, int32_t, double, int64_t, double>, Entry> map;
+    std::map<std::tuple<int, int64_t, int32_t, int32_t, double, int64_t, double, int32_t, double, double>, Entry> map;
     ~SingleCache() { clear(); }
     void clear()
     {
@@ -972,7 +1002,8 @@ fif_status single(const T* x, int64_t N, fif_window window, double delta, int32_
     HIP_TRY(hipGetDevice(&dev));
     auto& C = single_cache();
     std::lock_guard<std::mutex> lock(C.mu);
-    auto key = std::make_tuple(dev, N, max_imfs, opt.mask_rule, opt.nu, opt.max_inner, opt.floor_tau);
+    auto key = std::make_tuple(dev, N, max_imfs, opt.mask_rule, opt.nu, opt.max_inner, opt.floor_tau, opt.stop_mode,
+                               opt.gamma, opt.peak_rho);
     auto it = C.map.find(key);
     if (it == C.map.end()) {
         SingleCache::Entry e;

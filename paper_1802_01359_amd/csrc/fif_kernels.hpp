@@ -328,6 +328,13 @@ __device__ __forceinline__ double gain_pow(double lam, int64_t m)
     return exp((double)m * log1p(-lam));
 }
 
+// Thresholded gain: a bin whose factor is >= 1 - gamma is taken whole
+// (lambda replaced by 0); gamma = 0 leaves the gain unchanged.
+__device__ __forceinline__ double gain_th(double g, double gamma)
+{
+    return (gamma > 0.0 && g >= 1.0 - gamma) ? 1.0 : g;
+}
+
 // --------------------------------------------------------------- tables --
 
 __global__ void k_fill_sin(double* __restrict__ out, int64_t N, int64_t count)
@@ -442,6 +449,7 @@ struct StepArgs {
     const double* dtab;    // sine tables
     const double2* ctab;   // twiddle tables
     const int32_t* itab;   // storage position <-> bin maps
+    double gamma;          // > 0: thresholded IMF
     double2* spec0;
     double2* spec1;
     double2* inter;
@@ -510,7 +518,7 @@ __global__ __launch_bounds__(kFftThreads) void k_single(StepArgs A, const InT* _
     for (int j = threadIdx.x; j <= nh; j += kFftThreads) {
         const double2 v = Rin[j];
         double g = 0.0;
-        if (MODE == MODE_STEP) g = gain_pow(lambda_at(j, lw), m);
+        if (MODE == MODE_STEP) g = gain_th(gain_pow(lambda_at(j, lw), m), A.gamma);
         lds[j] = step_input(v, false, g, invN);
         if (j != 0 && 2 * j != N) lds[N - j] = step_input(v, true, g, invN);
         if (MODE == MODE_STEP) Rout[j] = cscale(v, 1.0 - g);
@@ -731,7 +739,7 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
                 const int64_t pk = (f < owners) ? pbase + f : (N >> 1);
                 const double2 v = vv[q];
                 double g = 0.0;
-                if (MODE == MODE_STEP) g = gain_pow(lambda_at(k, lw), m);
+                if (MODE == MODE_STEP) g = gain_th(gain_pow(lambda_at(k, lw), m), A.gamma);
                 lds[r * TC + s] = step_input(v, false, g, invN);
                 if (f < owners) {
                     int ms, mr;
@@ -756,7 +764,7 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
                 const int64_t j = mirror ? N - k : k;
                 const double2 v = Rin[j];
                 double g = 0.0;
-                if (MODE == MODE_STEP) g = gain_pow(lambda_at(j, lw), m);
+                if (MODE == MODE_STEP) g = gain_th(gain_pow(lambda_at(j, lw), m), A.gamma);
                 lds[f] = step_input(v, mirror, g, invN);
                 if (MODE == MODE_STEP && !mirror) Rout[j] = cscale(v, 1.0 - g);
             }
@@ -939,11 +947,13 @@ struct ScanArgs {
     double nu;
     int64_t max_inner;
     double floor_tau;
+    int stop_mode;            // 0 SD, 1 absolute step norm, 2 a-priori N0
 };
 
-__device__ __forceinline__ int64_t mask_length(int64_t N, int64_t k, int rule, double nu)
+__device__ __forceinline__ int64_t mask_length(int64_t N, int64_t k, int rule, double nu, int64_t fpeak)
 {
     if (rule == 0) return (2 * N + k - 1) / k;
+    if (rule == 2) return (N + fpeak - 1) / fpeak;
     const int64_t L = 2 * (int64_t)floor(nu * (double)N / (double)k);
     return L < 1 ? 1 : L;
 }
@@ -1006,12 +1016,43 @@ __device__ __forceinline__ void scan_prologue(const ScanArgs& A, int s, const Si
                 sh_i[0] = -1;
             } else {
                 S->k = r.cnt;
-                sh_i[0] = mask_length(N, r.cnt, A.mask_rule, A.nu);
+                sh_i[0] = mask_length(N, r.cnt, A.mask_rule, A.nu, S->fpeak);
             }
             sh_d[0] = S->pscale;
         }
         __syncthreads();
     }
+}
+
+// Spectral-peak bin of every active signal s0 + b (mask rule 2): the highest
+// bin f in [1, N/2] with |R_f|^2 >= rho max_{1<=j<=N/2} |R_j|^2, or 1 when
+// those bins are all zero.  Storage positions 1..N/2 hold bins 1..N/2.
+__global__ __launch_bounds__(256) void k_peak(ScanArgs A, int s0, double rho)
+{
+    __shared__ double shd[2 * 4];
+    const int s = s0 + blockIdx.x;
+    SigState* S = A.st + s;
+    if (!S->active) return;
+    const SigDesc d = A.sigs[s];
+    const LenPlan& lp = A.lens[d.len_id];
+    const int32_t* btab = lp.spec_perm ? A.itab + lp.bin_off : nullptr;
+    const double2* R = ((A.t & 1) ? A.spec1 : A.spec0) + d.spec_off;
+    const int64_t nh = d.N / 2;
+    double mn = INFINITY, mx = 0.0;
+    for (int64_t p = 1 + threadIdx.x; p <= nh; p += 256) {
+        const double2 z = R[p];
+        mx = fmax(mx, z.x * z.x + z.y * z.y);
+    }
+    block_minmax<256>(mn, mx, shd);
+    const double thr = rho * mx;
+    double best = 0.0;
+    mn = INFINITY;
+    for (int64_t p = 1 + threadIdx.x; p <= nh; p += 256) {
+        const double2 z = R[p];
+        if (z.x * z.x + z.y * z.y >= thr) best = fmax(best, (double)(btab ? (int64_t)btab[p] : p));
+    }
+    block_minmax<256>(mn, best, shd);
+    if (threadIdx.x == 0) S->fpeak = (mx > 0.0 && best >= 1.0) ? (int64_t)best : 1;
 }
 
 // The start of an outer step alone, for the proposal path: the network needs
@@ -1037,8 +1078,9 @@ __device__ __forceinline__ int64_t geo_m(int q) { return q == 0 ? 1 : q == 1 ? 2
 // One workgroup per signal with at most BPT * kScanThreads bins: thread-owned
 // bins j = 1 + tid + i*T (i < BPT) keep log2(mu) and the power in registers,
 // power*lambda^2 in LDS.  PRE: k_scan_prologue already ran (L and the power
-// scale are in the signal state).
-template <int BPT, bool PRE>
+// scale are in the signal state).  SMODE: the stop mode (a compile-time copy
+// of ScanArgs::stop_mode, so the default kernel carries no other mode's work).
+template <int BPT, bool PRE, int SMODE>
 __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
 {
     constexpr int T = kScanThreads;
@@ -1077,6 +1119,12 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
     const float lnd2 = logf(d2f);
     const int64_t cap = A.max_inner;
     uint32_t n32 = 0, n64 = 0;
+    // stop mode 1: ||s_{m+1} - s_m||^2 = sum_j P_j lambda_j^2 mu_j^m / (N pscale)
+    constexpr bool absm = SMODE == 1;
+    const double inv_np = 1.0 / ((double)N * pscale);
+    const float lnthr_abs = (float)log(delta * delta * (double)N * pscale);
+    auto ok = [&](double sd) { return SMODE != 0 ? sd < delta : sd <= delta; };
+    double mz = 0.0;          // largest |R_j|^2 (stop mode 2)
 
     // ---- first sweep: FP32 copies of the weighted power b, power*lambda^2
     //      a, and tau = log2 mu, mu = (1 - lambda)^2 (DC kept aside since
@@ -1111,6 +1159,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
             if (j <= nh) {
                 v[g] = R[pos_small(smap, j)];
                 jb[g] = j;
+                if (SMODE == 2) mz = fmax(mz, v[g].x * v[g].x + v[g].y * v[g].y);
             }
         }
 #pragma unroll
@@ -1139,8 +1188,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
     // form 0 * tau with tau = -inf for bins whose FP32 lambda rounds to 1)
     auto f32 = [&](int64_t m) -> float {
         float v[2] = {0.f, 0.f};
-        const float e = (float)(m - 1);
-        if (m == 1) {
+        const float e = (float)(absm ? m : m - 1);
+        if (m == 1 && !absm) {
 #pragma unroll
             for (int i = 0; i < NR; ++i) {
                 v[0] += lds_a[i * T + tid];
@@ -1150,12 +1199,13 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
 #pragma unroll
             for (int i = 0; i < NR; ++i) acc_bin(tau_r[i], lds_a[i * T + tid], b_r[i], e, v[0], v[1]);
         }
-        if (m == 1 && tid == 0) {
+        if (m == 1 && !absm && tid == 0) {
             v[0] += (float)P0;
             v[1] += (float)P0;
         }
         block_sum<float, T, 2>(v, shf);
         n32 += 1;
+        if (absm) return v[0] > 0.f ? (logf(v[0]) - lnthr_abs) : -INFINITY;
         return v[1] > 0.f ? (logf(v[0] / v[1]) - lnd2) : -INFINITY;
     };
 
@@ -1164,7 +1214,47 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
     //      regula falsi: smallest m <= cap with f(m) <= 0 (f is
     //      non-increasing in m)
     int64_t mt;
-    {
+    uint32_t flags = 0;
+    if (SMODE == 2) {
+        // Theorem 5: smallest N0 >= 1 with N0^N0 / (N0+1)^(N0+1) <
+        // delta / (||U^T r||_inf sqrt(N - 1 - k)), k = gcd(L, N) - 1 zero
+        // eigenvalues, compared in logarithms (every thread alike)
+        double mn_unused = INFINITY, mzb = fmax(mz, P0 / pscale);
+        block_minmax<T>(mn_unused, mzb, shd);
+        int64_t ga = L, gb = N;
+        while (gb) {
+            const int64_t r = ga % gb;
+            ga = gb;
+            gb = r;
+        }
+        const int64_t rest = N - 1 - (ga - 1);
+        const double st_inf = sqrt(mzb / (double)N);
+        int64_t n0 = 1;
+        if (st_inf > 0.0 && rest > 0) {
+            const double rhs = log(delta / (st_inf * sqrt((double)rest)));
+            auto lhs = [](int64_t n) { return (double)n * log((double)n) - (double)(n + 1) * log((double)(n + 1)); };
+            int64_t hi2 = 1;
+            while (lhs(hi2) >= rhs && hi2 < ((int64_t)1 << 50)) hi2 *= 2;
+            int64_t lo2 = hi2 / 2;
+            if (lo2 == 0) {
+                n0 = 1;
+            } else {
+                while (hi2 - lo2 > 1) {
+                    const int64_t mid = (lo2 + hi2) / 2;
+                    if (lhs(mid) < rhs)
+                        hi2 = mid;
+                    else
+                        lo2 = mid;
+                }
+                n0 = hi2;
+            }
+        }
+        mt = n0;
+        if (mt > cap) {
+            mt = cap;
+            flags |= FIF_IMF_CAP;
+        }
+    } else {
         int64_t lo = 0, hi = -1;
         float flo = INFINITY, fhi = 0.f;
         const int64_t mp = A.prop ? A.prop[s] : 0;
@@ -1322,28 +1412,38 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
         n64 += 1;
         sd_m = v[3] > 0.0 ? sqrt(v[2] / v[3]) : 0.0;
         sd_mm1 = (m == 1) ? INFINITY : (v[1] > 0.0 ? sqrt(v[0] / v[1]) : 0.0);
+        if (SMODE != 0) {
+            // called with m + 1: the numerators are sum P lambda^2 mu^m and
+            // sum P lambda^2 mu^(m-1), i.e. ||s_{m+1} - s_m||^2 and
+            // ||s_m - s_{m-1}||^2 times N pscale
+            sd_m = sqrt(v[2] * inv_np);
+            sd_mm1 = sqrt(v[0] * inv_np);
+        }
     };
+    // FP64 stop quantities at m and m - 1 for the active stop mode
+    auto stop64 = [&](int64_t m, double& sd_m, double& sd_mm1) { sd64(SMODE != 0 ? m + 1 : m, sd_m, sd_mm1); };
 
     // ---- FP64 confirmation of mt (SD_mt <= delta < SD_{mt-1}); otherwise an
     //      exact FP64 gallop + bisection from mt, then a final evaluation
-    uint32_t flags = 0;
     int64_t m = mt;
     double sd_m = 0.0, sd_p = 0.0;
-    {
+    if (SMODE == 2) {
+        stop64(m, sd_m, sd_p);      // reported only; m is the a-priori count
+    } else {
         // stage 0 confirm, 1 gallop up, 2 gallop down, 3 bisect, 4 final
         int stage = 0;
         int64_t cand = mt, elo = 0, ehi = -1, gstep = 1;
         while (true) {
             double sm, sp;
-            sd64(cand, sm, sp);
-            const bool okm = sm <= delta;
+            stop64(cand, sm, sp);
+            const bool okm = ok(sm);
             if (stage == 4) {
                 sd_m = sm;
                 sd_p = sp;
                 break;
             }
             if (stage == 0) {
-                const bool okp = sp <= delta;
+                const bool okp = ok(sp);
                 if (okm && !okp) {
                     m = cand;
                     sd_m = sm;
@@ -1414,7 +1514,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
             }
         }
     }
-    if (sd_m > delta) flags |= FIF_IMF_CAP;
+    if (SMODE != 2 && !ok(sd_m)) flags |= FIF_IMF_CAP;
 
     if (tid == 0) {
         S->L = L;

@@ -89,6 +89,7 @@ struct RunState {
 // Mutable per-signal state in the workspace.
 struct SigState {
     int64_t k, L, m;
+    int64_t fpeak;                 // spectral-peak bin of this step (mask rule 2)
     double sd, sd_prev;
     double mean, maxabs, pscale;
     // min / max of the residual of the current outer step as order-preserving

@@ -48,6 +48,7 @@ def test_options_default(lib):
     o = _Options()
     lib.fif_options_default(ctypes.byref(o))
     assert (o.mask_rule, o.nu, o.max_inner, o.floor_tau) == (0, 1.6, 1_000_000, 1e-9)
+    assert (o.stop_mode, o.gamma, o.peak_rho) == (0, 0.0, 0.1)
 
 
 def _plan_status(lib, lengths, max_imfs=4, **opt):
@@ -71,6 +72,13 @@ def _plan_status(lib, lengths, max_imfs=4, **opt):
     ([4096], dict(mask_rule=1, nu=-1.0), -1),
     ([4096], dict(max_inner=0), -1),
     ([4096], dict(floor_tau=-1.0), -1),
+    ([4096], dict(stop_mode=3), -1),
+    ([4096], dict(gamma=1.0), -1),
+    ([4096], dict(gamma=-0.1), -1),
+    ([4096], dict(mask_rule=2, peak_rho=0.0), -1),
+    ([4096], dict(mask_rule=2, peak_rho=1.5), -1),
+    ([4096, 131072], dict(stop_mode=1), -1),   # stop modes 1, 2: lengths <= 65536
+    ([262144], dict(stop_mode=2), -1),
     ([], {}, -1),
 ])
 def test_plan_rejects_bad_arguments_on_host(lib, lengths, kw, status):

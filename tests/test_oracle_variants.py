@@ -20,6 +20,17 @@ def _tone(N, k0, amp=1.0, phase=0.3):
     return amp * np.cos(2 * np.pi * k0 * i / N + phase)
 
 
+# ----------------------------------------------- closed-form eigenvalues --
+
+@pytest.mark.parametrize("N,L", [(64, 3), (128, 6), (1000, 17), (4096, 21), (4096, 2048), (97, 200)])
+def test_closed_form_eigenvalues_equal_the_column_dft(N, L):
+    """eq. "eig2" against the DFT of the window column (eq. "Lambdas")."""
+    a = fs.eigenvalues_closed(N, L)
+    b = fs.eigenvalues(N, L)
+    assert np.max(np.abs(a - b)) <= 1e-14
+    assert a[0] == 1.0 and np.all(a >= 0.0) and np.all(a <= 1.0)
+
+
 # ------------------------------------------------------- absolute criterion --
 
 @pytest.mark.parametrize("delta", [1e-1, 1e-2, 3e-3])
