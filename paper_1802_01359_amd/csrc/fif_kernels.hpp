@@ -888,27 +888,56 @@ __global__ __launch_bounds__(kFftThreads) void k_pass2(StepArgs A, const InT* __
         return;
     }
     OutT* row = imfs + (int64_t)A.max_imfs * d.off + (int64_t)A.t * N;
-    for (int f = threadIdx.x; f < total; f += kFftThreads) {
-        int rl;
-        const int cp = fdivmod(f, ftr, rl);
-        row[(int64_t)N2 * cp + r0 + rl] = (OutT)lds[f].x;
+    // IMF row out of the real parts; the imaginary parts (the residual) are
+    // kept in registers
+    constexpr int EQ = kTileCap / kFftThreads;
+    double yv[EQ];
+#pragma unroll
+    for (int q = 0; q < EQ; ++q) {
+        const int f = threadIdx.x + q * kFftThreads;
+        yv[q] = 0.0;
+        if (f < total) {
+            int rl;
+            const int cp = fdivmod(f, ftr, rl);
+            const double2 v = lds[f];
+            row[(int64_t)N2 * cp + r0 + rl] = (OutT)v.x;
+            yv[q] = v.y;
+        }
     }
     if (d.resid_off >= 0) {
         // thin row tiles: hand the residual to k_count_resid
         double* y = A.resid + d.resid_off;
-        for (int f = threadIdx.x; f < total; f += kFftThreads) {
-            int rl;
-            const int cp = fdivmod(f, ftr, rl);
-            y[(int64_t)N2 * cp + r0 + rl] = lds[f].y;
+#pragma unroll
+        for (int q = 0; q < EQ; ++q) {
+            const int f = threadIdx.x + q * kFftThreads;
+            if (f < total) {
+                int rl;
+                const int cp = fdivmod(f, ftr, rl);
+                y[(int64_t)N2 * cp + r0 + rl] = yv[q];
+            }
         }
         return;
     }
+    // the residual again in LDS, column cp at stride TR + 1 so that the
+    // per-column reads below fall in different banks
+    __syncthreads();
+    double* yp = reinterpret_cast<double*>(lds);
+#pragma unroll
+    for (int q = 0; q < EQ; ++q) {
+        const int f = threadIdx.x + q * kFftThreads;
+        if (f < total) {
+            int rl;
+            const int cp = fdivmod(f, ftr, rl);
+            yp[cp * (TR + 1) + rl] = yv[q];
+        }
+    }
+    __syncthreads();
     const int runs_per_row = N2 / TR;
     double mn = INFINITY, mx = -INFINITY;
     for (int cp = threadIdx.x; cp < N1; cp += kFftThreads) {
         RunState r = run_empty();
         for (int rl = 0; rl < TR; ++rl) {
-            const double y = lds[cp * TR + rl].y;
+            const double y = yp[cp * (TR + 1) + rl];
             run_push(r, y);
             mn = fmin(mn, y);
             mx = fmax(mx, y);
