@@ -933,7 +933,7 @@ fif_status batched(fif_plan* p, const T* x, double delta, T* imfs, T* rem, int32
     // outer steps: one stream per signal group (forked from and joined back
     // to the caller's stream); a single group when the proposal network or
     // feature recording is on (they share buffers across signals) or while
-    // profiling (per-kernel times)
+    // profiling (each kernel then runs alone and its events time it alone)
     const int G = (p->model || p->rec || p->prof) ? 1 : (int)p->groups.size();
     if (G <= 1) {
         for (int t = 0; t < p->max_imfs; ++t) launch_step<T>(p, b, t, x, imfs, ws, s, p->all);
