@@ -114,7 +114,7 @@ def peak_frequency(R, rho: float) -> int:
 
 def decompose(s, delta: float, max_imfs: int, *, mask_rule: int = 0, nu: float = 1.6,
               max_inner: int = 1_000_000, floor_tau: float = 1e-9, stop: str = "sd",
-              gamma: float = 0.0, peak_rho: float = 0.1) -> dif.Decomposition:
+              gamma: float = 0.0, peak_rho: float = 0.1, search: str = "linear") -> dif.Decomposition:
     s = np.ascontiguousarray(np.asarray(s, dtype=np.float64))
     N = s.size
     r = s.copy()
@@ -143,7 +143,34 @@ def decompose(s, delta: float, max_imfs: int, *, mask_rule: int = 0, nu: float =
         mu = (1.0 - lam) ** 2
         lam2 = lam * lam
         flags = 0
-        if stop == "sd":
+        if stop == "sd" and search == "bisect":
+            # SD_m is non-increasing in m, so the smallest m with SD_m <= delta
+            # is found by doubling then bisection on the same Parseval sums
+            def sd_at(mm):
+                if mm == 1:
+                    num, den = float(np.sum(P * lam2)), float(np.sum(P))
+                else:
+                    x = P * _pow1m(lam, 2 * (mm - 1))
+                    num, den = float(np.sum(x * lam2)), float(np.sum(x))
+                return math.sqrt(num / den) if den > 0 else 0.0
+            hi = 1
+            while sd_at(hi) > delta and hi < max_inner:
+                hi = min(max_inner, 2 * hi)
+            if sd_at(hi) > delta:
+                m = max_inner
+                flags |= dif.FLAG_CAP
+            else:
+                lo = hi // 2 if hi > 1 else 0          # sd_at(lo) > delta (lo = 0: none)
+                while hi - lo > 1:
+                    mid = (lo + hi) // 2
+                    if sd_at(mid) <= delta:
+                        hi = mid
+                    else:
+                        lo = mid
+                m = hi
+            sd = sd_at(m)
+            sd_prev = sd_at(m - 1) if m > 1 else math.inf
+        elif stop == "sd":
             # N0 = 1, 2, ...: SD_{N0} = ||(1-lam)^{N0-1} lam R|| / ||(1-lam)^{N0-1} R||
             x = P.copy()
             m = 0

@@ -271,3 +271,68 @@ def test_chirp_batch_full_size_sampled():
         s64 = sigs[b].astype(np.float64)
         _check(ref, s64, out.imfs_of(b).cpu().numpy().astype(np.float64),
                out.remainder_of(b).cpu().numpy().astype(np.float64), info[b], int(n[b]), 1e-3, False)
+
+
+def _spectral_many(signals, delta, max_imfs):
+    from oracle import fif_spectral
+    with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        futs = [ex.submit(fif_spectral.decompose, s, delta, max_imfs, search="bisect") for s in signals]
+        return [f.result() for f in futs]
+
+
+def test_uneven_batch_full_size_sampled():
+    """The benchmark's uneven configuration: 4096 FP32 signals, 7-smooth
+    lengths log-uniform in [1024, 262144], delta 1e-4, 12 IMFs. Every signal
+    reconstructs; six signals spread over the lengths are checked against the
+    spectral oracle (bisection search: its m is pinned to the linear scan's)."""
+    L = [int(n) for n in siggen.uneven_lengths(4096)]
+    print("case uneven batch B=%d total=%d" % (len(L), sum(L)), flush=True)
+    sigs = [siggen.uneven_signal(i, n).astype(np.float32) for i, n in enumerate(L)]
+    plan, packed, out = _run_batch(L, sigs, 1e-4, 12, torch.float32)
+    assert int(out.sig_status.abs().sum()) == 0
+    info = out.info()
+    n = out.n_imfs.cpu().numpy()
+    assert np.all(info["flags"] & 4 == 0)
+    worst = 0.0
+    for b in range(len(L)):
+        x = packed[int(out.offsets[b]):int(out.offsets[b + 1])].double()
+        rec = out.imfs_of(b).double().sum(0) + out.remainder_of(b).double()
+        worst = max(worst, float((rec - x).norm() / x.norm()))
+    assert worst < 1e-6, worst
+    order = np.argsort(L)
+    picks = [int(order[i]) for i in (0, len(L) // 4, len(L) // 2, 3 * len(L) // 4, len(L) - 2, len(L) - 1)]
+    print("  spectral oracle for signals %s lengths %s" % (picks, [L[b] for b in picks]), flush=True)
+    refs = _spectral_many([sigs[b].astype(np.float64) for b in picks], 1e-4, 12)
+    for b, ref in zip(picks, refs):
+        s64 = sigs[b].astype(np.float64)
+        _check(ref, s64, out.imfs_of(b).cpu().numpy().astype(np.float64),
+               out.remainder_of(b).cpu().numpy().astype(np.float64), info[b], int(n[b]), 1e-4, False)
+
+
+def test_long_signal_full_size():
+    """The benchmark's long configuration: one FP32 signal of 2^24 samples,
+    delta 1e-3, 20 IMFs. Reconstruction and zero-mean IMFs over the whole
+    decomposition; the first three IMFs against the spectral oracle."""
+    s = siggen.long_drift().astype(np.float32)
+    N = s.size
+    print("case long N=%d" % N, flush=True)
+    plan, packed, out = _run_batch([N], [s], 1e-3, 20, torch.float32)
+    info = out.info()[0]
+    nn = int(out.n_imfs.cpu().numpy()[0])
+    assert nn >= 3 and np.all(info["flags"] & 4 == 0)
+    im = out.imfs_of(0).double()
+    rec = im.sum(0) + out.remainder_of(0).double()
+    x = packed.double()
+    assert float((rec - x).norm() / x.norm()) < 1e-6
+    means = im[:nn].mean(1).abs().cpu().numpy()
+    assert np.all(means <= 1e-6 * float(x.abs().max()))
+    print("  spectral oracle, 3 IMFs", flush=True)
+    from oracle import fif_spectral
+    ref = fif_spectral.decompose(s.astype(np.float64), 1e-3, 3, search="bisect")
+    imfs = out.imfs_of(0).cpu().numpy()[:3].astype(np.float64)
+    ref_delta[0] = 1e-3
+    same, tie_at = _decisions_match(ref, info[:3], min(nn, 3))
+    upto = 3 if same else tie_at
+    for j in range(upto):
+        a = ref.imfs[j]
+        assert np.linalg.norm(a - imfs[j]) <= 1e-5 * np.linalg.norm(a), j

@@ -31,6 +31,19 @@ def test_closed_form_eigenvalues_equal_the_column_dft(N, L):
     assert a[0] == 1.0 and np.all(a >= 0.0) and np.all(a <= 1.0)
 
 
+# ------------------------------------------------------ bisection search --
+
+@pytest.mark.parametrize("delta", [1e-3, 1e-4])
+def test_bisection_search_equals_linear_scan(delta):
+    """SD_m is non-increasing, so bisection must find the linear scan's m."""
+    for s in (siggen.tones3(), siggen.chirps(3, N=8192), siggen.uneven_signal(5, 6000)):
+        a = fs.decompose(s, delta, 6)
+        b = fs.decompose(s, delta, 6, search="bisect")
+        assert (a.k, a.L, a.m) == (b.k, b.L, b.m)
+        assert np.allclose(a.sd, b.sd, rtol=1e-9, atol=0)
+        assert np.max(np.abs(a.imfs - b.imfs)) <= 1e-12 * np.max(np.abs(s))
+
+
 # ------------------------------------------------------- absolute criterion --
 
 @pytest.mark.parametrize("delta", [1e-1, 1e-2, 3e-3])
