@@ -14,8 +14,9 @@
 //
 //   k_bscan_decide one small workgroup per signal after every round: adds the
 //                  per-tile partial sums in tile order and picks the next
-//                  candidates -- evenly spaced inside the bracket, or a
-//                  gallop when no candidate satisfies the test yet.
+//                  candidates -- up to kBigRefine evenly spaced inside the
+//                  bracket, or a gallop when no candidate satisfies the test
+//                  yet.
 // Signals already decided skip the remaining launches.  Partial sums cross
 // workgroups only through kernel boundaries (no device-scope fences).
 #pragma once
@@ -122,6 +123,22 @@ __global__ void k_bscan_seed(ScanArgs A)
 // out[2i] = sum a x, out[2i+1] = sum b x (shared memory, all threads).
 // FP32 phases: x = 2^((m-1) tau) from scratch; FP64 phase: mu^(m-1) from the
 // spectrum with FP64 lambda, two candidates at a time.
+// One level of a reduce-scatter over the 64 lanes of a wave: a lane holding
+// 2S values keeps the lower S (lane bit S clear) or the upper S (set), adds
+// the partner's copy of the same S (partner = lane ^ S) and drops the rest.
+template <int S>
+__device__ __forceinline__ void wave_reduce_scatter(float* v, int lane)
+{
+    const bool up = (lane & S) != 0;
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+        const float lo = v[i], hi = v[i + S];
+        const float send = up ? lo : hi;
+        const float keep = up ? hi : lo;
+        v[i] = keep + __shfl_xor(send, S);
+    }
+}
+
 template <int T, int BPT>
 __device__ __forceinline__ void bscan_tile_sums(const ScanArgs& A, const SigDesc& d, const LenPlan& lp,
                                                 const BigScan* G, int tile, double* out, float* shf,
@@ -143,10 +160,24 @@ __device__ __forceinline__ void bscan_tile_sums(const ScanArgs& A, const SigDesc
         float acc[2 * kBigCand];
 #pragma unroll
         for (int i = 0; i < 2 * kBigCand; ++i) acc[i] = 0.f;
+        // all of the thread's bins are loaded first (one memory round trip);
+        // bins past the end of the signal carry a = b = 0
+        float tq[BPT], aq[BPT], bq[BPT];
+#pragma unroll
         for (int q = 0; q < BPT; ++q) {
             const int j = j0 + tid + q * T;
-            if (j > nh) break;
-            const float tj = tau[j - 1], aj = av[j - 1], bj = bv[j - 1];
+            tq[q] = 0.f;
+            aq[q] = 0.f;
+            bq[q] = 0.f;
+            if (j <= nh) {
+                tq[q] = tau[j - 1];
+                aq[q] = av[j - 1];
+                bq[q] = bv[j - 1];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < BPT; ++q) {
+            const float tj = tq[q], aj = aq[q], bj = bq[q];
 #pragma unroll
             for (int i = 0; i < kBigCand; ++i) {
                 if (i < nc) {
@@ -156,18 +187,24 @@ __device__ __forceinline__ void bscan_tile_sums(const ScanArgs& A, const SigDesc
                 }
             }
         }
+        // the 2*kBigCand sums over the workgroup: a reduce-scatter across the
+        // wave (each level halves the values a lane keeps, so lane l ends with
+        // the wave's sum of value l), then the waves' sums in wave order
+        static_assert(2 * kBigCand == 64, "one value per lane after the reduce-scatter");
+        const int lane = tid & 63, wave = tid >> 6;
+        wave_reduce_scatter<32>(acc, lane);
+        wave_reduce_scatter<16>(acc, lane);
+        wave_reduce_scatter<8>(acc, lane);
+        wave_reduce_scatter<4>(acc, lane);
+        wave_reduce_scatter<2>(acc, lane);
+        wave_reduce_scatter<1>(acc, lane);
+        shf[wave * 64 + lane] = acc[0];
+        __syncthreads();
+        if (tid < 64) {
+            float s = 0.f;
 #pragma unroll
-        for (int c = 0; c < kBigCand; c += 4) {
-            if (c < nc) {
-                float v8[8];
-#pragma unroll
-                for (int k = 0; k < 8; ++k) v8[k] = acc[2 * c + k];
-                block_sum<float, T, 8>(v8, shf);
-                if (tid == 0) {
-#pragma unroll
-                    for (int k = 0; k < 8; ++k) out[2 * c + k] = (double)v8[k];
-                }
-            }
+            for (int w = 0; w < T / 64; ++w) s += shf[w * 64 + tid];
+            out[tid] = (double)s;
         }
     } else {
         const Lam lw = make_lam(lp, A.dtab, G->L);
@@ -178,11 +215,25 @@ __device__ __forceinline__ void bscan_tile_sums(const ScanArgs& A, const SigDesc
             const int64_t e0 = G->cand[c] - 1;
             const int64_t e1 = (c + 1 < nc) ? G->cand[c + 1] - 1 : -1;
             double acc[4] = {0.0, 0.0, 0.0, 0.0};
-            for (int q = 0; q < BPT; ++q) {
-                const int j = j0 + tid + q * T;
-                if (j > nh) break;
-                const double2 z = R[j];                // storage position j
-                const int64_t jb = (btab ? (int64_t)btab[j] : (int64_t)j);    // its bin
+            constexpr int DG = 4;  // bins whose loads are issued together
+            for (int q0 = 0; q0 < BPT; q0 += DG) {
+              double2 zz[DG];
+              int64_t jj[DG];
+#pragma unroll
+              for (int g = 0; g < DG; ++g) {
+                const int j = j0 + tid + (q0 + g) * T;
+                zz[g] = make_double2(0.0, 0.0);
+                jj[g] = 1;
+                if (j <= nh) {
+                    zz[g] = R[j];                      // storage position j
+                    jj[g] = btab ? (int64_t)btab[j] : (int64_t)j;   // its bin
+                }
+              }
+#pragma unroll
+              for (int g = 0; g < DG; ++g) {
+                if (j0 + tid + (q0 + g) * T > nh) break;
+                const double2 z = zz[g];
+                const int64_t jb = jj[g];
                 const double P = ((2 * jb == d.N) ? 1.0 : 2.0) * (z.x * z.x + z.y * z.y) * pscale;
                 const double lam = lambda_at(jb, lw);
                 const double l2 = lam * lam;
@@ -202,6 +253,7 @@ __device__ __forceinline__ void bscan_tile_sums(const ScanArgs& A, const SigDesc
                 acc[1] += P * x0;
                 acc[2] += P * l2 * x1;
                 acc[3] += P * x1;
+              }
             }
             block_sum<double, T, 4>(acc, shd);
             if (tid == 0) {
@@ -355,7 +407,7 @@ __global__ __launch_bounds__(T) void k_bscan_round(ScanArgs A, const Work* __res
 {
     constexpr int BPT = kBigTile / T;
     __shared__ double shd[4 * (T / 64)];
-    __shared__ float shf[8 * (T / 64)];
+    __shared__ float shf[64 * (T / 64)];
     __shared__ double shv[2 * kBigCand];
     const Work w = work[blockIdx.x];
     const SigDesc d = A.sigs[w.sig];
@@ -373,16 +425,32 @@ __global__ __launch_bounds__(T) void k_bscan_round(ScanArgs A, const Work* __res
         // position -> bin table of this length, read once (null: bin order)
         const int32_t* btab = lp.spec_perm ? A.itab + lp.bin_off : nullptr;
         const double pscale = G->pscale;
-        for (int q = 0; q < BPT; ++q) {
-            const int j = 1 + w.tile * kBigTile + threadIdx.x + q * T;
+        constexpr int SG = 4;  // bins whose loads are issued together
+        for (int q0 = 0; q0 < BPT; q0 += SG) {
+          double2 zz[SG];
+          int64_t jj[SG];
+#pragma unroll
+          for (int g = 0; g < SG; ++g) {
+            const int j = 1 + w.tile * kBigTile + threadIdx.x + (q0 + g) * T;
+            zz[g] = make_double2(0.0, 0.0);
+            jj[g] = 1;
+            if (j <= nh) {
+                zz[g] = R[j];
+                jj[g] = btab ? (int64_t)btab[j] : (int64_t)j;
+            }
+          }
+#pragma unroll
+          for (int g = 0; g < SG; ++g) {
+            const int j = 1 + w.tile * kBigTile + threadIdx.x + (q0 + g) * T;
             if (j > nh) break;
-            const double2 z = R[j];                    // storage position j
-            const int64_t jb = (btab ? (int64_t)btab[j] : (int64_t)j);        // its bin
+            const double2 z = zz[g];                   // storage position j
+            const int64_t jb = jj[g];                  // its bin
             const double P = ((2 * jb == d.N) ? 1.0 : 2.0) * (z.x * z.x + z.y * z.y) * pscale;
             const double lam = lambda_at(jb, lw);
             bv[j - 1] = (float)P;
             av[j - 1] = (float)(P * lam * lam);
             tau[j - 1] = 2.8853900817779268f * log1pf(-(float)lam);
+          }
         }
         // each thread reads back only its own bins below: no barrier needed
     }

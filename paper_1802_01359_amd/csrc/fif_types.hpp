@@ -63,7 +63,7 @@ struct SigDesc {
 // Multi-workgroup search for m (signals with more than one workgroup's bins).
 constexpr int kBigTile = 8192;     // bins per workgroup
 constexpr int kBigCand = 32;       // most candidates in one round (geometric probe, gallop)
-constexpr int kBigRefine = 7;      // candidates per round inside a bracket (octal search)
+constexpr int kBigRefine = 31;     // candidates per round inside a bracket
 constexpr int kBigRounds = 16;     // candidate rounds launched per outer step
 constexpr int kBigInactive = 4;    // phase of a signal that is not searching
 struct BigScan {
