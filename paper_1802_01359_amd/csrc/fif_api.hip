@@ -135,7 +135,8 @@ struct fif_plan {
     int32_t* d_itab = nullptr;
     // workspace layout (byte offsets)
     size_t ws_state = 0, ws_spec0 = 0, ws_spec1 = 0, ws_inter = 0, ws_parts = 0, ws_psum = 0, ws_gscr = 0,
-           ws_bigs = 0, ws_bpart = 0, ws_resid = 0, ws_feat = 0, ws_prop = 0, ws_total = 0;
+           ws_bigs = 0, ws_bpart = 0, ws_resid = 0, ws_feat = 0, ws_prop = 0, ws_chk = 0, ws_total = 0;
+    int32_t mt_shift = 0;           // test hook (FIF_DEBUG_MT_SHIFT): perturbs the deferred estimate
     // learned proposal of m, and recording of the network inputs
     fif_model* model = nullptr;
     uint16_t* rec = nullptr;
@@ -415,7 +416,7 @@ fif_status fif_plan_create(fif_plan** out, const int64_t* lengths, int32_t B, in
         d.bt_off = 0;
         d.n_btiles = 0;
         d.gs_off = 0;
-        d.pad = 0;
+        d.p1_off = (int32_t)p->w_p1.size();
         if (N / 2 > (int64_t)kScanBinsPerThread * kScanThreads) {
             d.bs = nbig++;
             d.bt_off = btiles;
@@ -526,6 +527,12 @@ fif_status fif_plan_create(fif_plan** out, const int64_t* lengths, int32_t B, in
     ws += sizeof(uint16_t) * (size_t)kNetFeat * kNetCin0 * (size_t)B;
     p->ws_prop = ws = align_up(ws, 256);
     ws += sizeof(int64_t) * (size_t)B;
+    p->ws_chk = ws = align_up(ws, 256);
+    ws += sizeof(double) * 4 * (p->w_p1.size() + 1);
+    {
+        const char* env = getenv("FIF_DEBUG_MT_SHIFT");
+        p->mt_shift = env ? atoi(env) : 0;
+    }
     p->ws_total = align_up(ws, 256);
 
     // metadata upload
@@ -677,6 +684,8 @@ Bound bind(const fif_plan* p, void* ws, double delta, fif_imf_info* info)
     A.ctab = p->d_ctab;
     A.itab = p->d_itab;
     A.gamma = p->opt.gamma;
+    A.chk = (double*)(w + p->ws_chk);
+    A.redo_only = 0;
     A.spec0 = (double2*)(w + p->ws_spec0);
     A.spec1 = (double2*)(w + p->ws_spec1);
     A.inter = (double2*)(w + p->ws_inter);
@@ -708,6 +717,10 @@ Bound bind(const fif_plan* p, void* ws, double delta, fif_imf_info* info)
     S.max_inner = p->opt.max_inner;
     S.floor_tau = p->opt.floor_tau;
     S.stop_mode = p->opt.stop_mode;
+    S.chk = A.chk;
+    S.defer = p->opt.stop_mode == 0 ? 1 : 0;
+    S.redo_only = 0;
+    S.mt_shift = p->mt_shift;
     return b;
 }
 
@@ -860,6 +873,20 @@ void launch_step(const fif_plan* p, Bound& b, int t, const T* x, T* imfs, void* 
         {
             Timed tm(p, "pass1_step", s);
             k_pass1<MODE_STEP, T><<<(unsigned)g.p1.count, kFftThreads, p->lds_p1, s>>>(A, x);
+        }
+        if (b.sc.defer && g.ssmall.count) {
+            // deferred FP64 check of m, then the rare redo: exact search and
+            // pass 1 again for the signals whose check failed
+            Timed tm(p, "verify", s);
+            ScanArgs V = b.sc;
+            V.t = t;
+            V.list = p->d_scan_small + g.ssmall.begin;
+            k_verify<<<(unsigned)((g.ssmall.count + 63) / 64), 64, 0, s>>>(V, g.ssmall.count);
+            V.redo_only = 1;
+            launch_k_scan<true>(0, g.ssmall.count, sizeof(float) * kScanBinsPerThread * kScanThreads, s, V);
+            StepArgs R = A;
+            R.redo_only = 1;
+            k_pass1<MODE_STEP, T><<<(unsigned)g.p1.count, kFftThreads, p->lds_p1, s>>>(R, x);
         }
         A.work = p->d_p2 + g.p2.begin;
         Timed tm(p, "pass2_step", s);

@@ -450,6 +450,8 @@ struct StepArgs {
     const double2* ctab;   // twiddle tables
     const int32_t* itab;   // storage position <-> bin maps
     double gamma;          // > 0: thresholded IMF
+    double* chk;           // deferred FP64 check: 4 partial sums per pass-1 work item
+    int redo_only;         // 1: only signals whose deferred check failed
     double2* spec0;
     double2* spec1;
     double2* inter;
@@ -690,6 +692,7 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
     const int N1 = lp.N1, N2 = lp.N2, TC = lp.TC;
     SigState* S = A.st + w.sig;
     if (MODE == MODE_STEP && !S->active) return;
+    if (MODE == MODE_STEP && A.redo_only && !S->redo) return;
     if (MODE == MODE_REMAINDER && S->status != 0) return;
     const int total = TC * N2;
     const FastDiv ftc = fastdiv(TC);
@@ -713,6 +716,9 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
             // spec_pos); all of a thread's loads are issued first
             constexpr int PQ = kTileCap / 2 / kFftThreads + 1;
             double2 vv[PQ];
+            // deferred FP64 check of m: this tile's part of the stop-test sums
+            const bool chk = MODE == MODE_STEP && S->chk;
+            double cs[4] = {0.0, 0.0, 0.0, 0.0};
             const int64_t pbase = (int64_t)w.tile * owners;
 #pragma unroll
             for (int q = 0; q < PQ; ++q) {
@@ -739,7 +745,31 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
                 const int64_t pk = (f < owners) ? pbase + f : (N >> 1);
                 const double2 v = vv[q];
                 double g = 0.0;
-                if (MODE == MODE_STEP) g = gain_th(gain_pow(lambda_at(k, lw), m), A.gamma);
+                if (MODE == MODE_STEP) {
+                    // (1-lambda)^m built from (1-lambda)^(m-2) so that the
+                    // deferred check gets mu^(m-1) and mu^(m-2) on the way
+                    const double lam = lambda_at(k, lw);
+                    double y, z;
+                    if (lam >= 1.0) {
+                        y = (m == 1) ? 1.0 : 0.0;
+                        z = (m == 2) ? 1.0 : 0.0;
+                        g = 0.0;
+                    } else {
+                        const double om = 1.0 - lam;
+                        z = (m >= 2) ? ((m == 2) ? 1.0 : gain_pow(lam, m - 2)) : 0.0;
+                        y = (m >= 2) ? z * om : 1.0;
+                        g = y * om;
+                    }
+                    if (chk) {
+                        const double P = ((2 * k == N) ? 1.0 : 2.0) * (v.x * v.x + v.y * v.y);
+                        const double l2 = lam * lam;
+                        cs[0] += P * l2 * y * y;
+                        cs[1] += P * y * y;
+                        cs[2] += P * l2 * z * z;
+                        cs[3] += P * z * z;
+                    }
+                    g = gain_th(g, A.gamma);
+                }
                 lds[r * TC + s] = step_input(v, false, g, invN);
                 if (f < owners) {
                     int ms, mr;
@@ -753,6 +783,14 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
                     if (!(c == 0 && r == 0)) lds[mr * TC + ms] = step_input(v, true, g, invN);
                 }
                 if (MODE == MODE_STEP) Rout[pk] = cscale(v, 1.0 - g);
+            }
+            if (chk) {
+                __shared__ double shc[4 * (kFftThreads / 64)];
+                block_sum<double, kFftThreads, 4>(cs, shc);
+                if (threadIdx.x < 4) {
+                    const double cv = threadIdx.x == 0 ? cs[0] : threadIdx.x == 1 ? cs[1] : threadIdx.x == 2 ? cs[2] : cs[3];
+                    A.chk[((int64_t)d.p1_off + w.tile) * 4 + threadIdx.x] = cv;
+                }
             }
         } else {
             const int64_t nh = N / 2;
@@ -813,6 +851,7 @@ __global__ __launch_bounds__(kFftThreads) void k_pass2(StepArgs A, const InT* __
     SigState* S = A.st + w.sig;
     const int total = TR * N1;
     const FastDiv ftr = fastdiv(TR);
+    if (MODE == MODE_STEP && w.tile == 0 && threadIdx.x == 0) S->redo = 0;   // the step is final now
     if (MODE == MODE_STEP && !S->active) {
         OutT* row = imfs + (int64_t)A.max_imfs * d.off + (int64_t)A.t * N;
         for (int f = threadIdx.x; f < total; f += kFftThreads) {
@@ -977,6 +1016,10 @@ struct ScanArgs {
     int64_t max_inner;
     double floor_tau;
     int stop_mode;            // 0 SD, 1 absolute step norm, 2 a-priori N0
+    double* chk;              // deferred FP64 check partials (StepArgs::chk)
+    int defer;                // 1: leave the FP64 check of paired four-step signals to pass 1
+    int redo_only;            // 1: only signals whose deferred check failed
+    int mt_shift;             // test hook: added to the deferred FP32 estimate
 };
 
 __device__ __forceinline__ int64_t mask_length(int64_t N, int64_t k, int rule, double nu, int64_t fpeak)
@@ -1124,6 +1167,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
     const SigDesc d = A.sigs[s];
     SigState* S = A.st + s;
     if (!S->active) return;
+    if (A.redo_only && !S->redo) return;
     const LenPlan& lp = A.lens[d.len_id];
     const int64_t N = d.N;
     const int tid = threadIdx.x;
@@ -1384,6 +1428,27 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
         }
     }
 
+    // ---- deferred FP64 check: paired four-step signals leave it to pass 1,
+    //      which reads the spectrum and forms the powers anyway; k_verify
+    //      accepts the estimate or sends the signal back here (redo_only)
+    if (SMODE == 0 && A.defer && !A.redo_only && lp.two_pass && lp.paired) {
+        if (A.mt_shift) mt = max((int64_t)1, min(cap, mt + (int64_t)A.mt_shift));
+        if (tid == 0) {
+            S->L = L;
+            S->m = mt;
+            S->chk = 1;
+            if (A.info) {
+                fif_imf_info* I = A.info + (int64_t)s * A.max_imfs + A.t;
+                I->k = S->k;
+                I->L = L;
+                I->m = mt;
+                I->flags = 0;
+                I->evals = (n32 & 0xffffu) | (1u << 16);
+            }
+        }
+        return;
+    }
+
     // ---- FP64 SD at m and m-1 (Parseval, FP64 lambda, powers and sums)
     auto sd64 = [&](int64_t m, double& sd_m, double& sd_mm1) {
         double v[4] = {0.0, 0.0, 0.0, 0.0};
@@ -1544,6 +1609,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
         }
     }
     if (SMODE != 2 && !ok(sd_m)) flags |= FIF_IMF_CAP;
+    if (A.redo_only) flags |= FIF_IMF_REFINED;   // the deferred check rejected the estimate
 
     if (tid == 0) {
         S->L = L;
@@ -1561,6 +1627,49 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
             I->flags = flags;
             I->evals = (n32 & 0xffffu) | (n64 << 16);
         }
+    }
+}
+
+// Deferred FP64 check of m (one thread per signal of the list): the pass-1
+// tiles' partial sums in tile order give SD_m and SD_{m-1}; the estimate is
+// kept if SD_m <= delta < SD_{m-1} (or m is the cap and SD_m > delta, as the
+// in-scan check decides), else the signal is marked for a redo.
+__global__ void k_verify(ScanArgs A, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int s = A.list[i];
+    SigState* S = A.st + s;
+    if (!S->active || !S->chk) return;
+    const SigDesc d = A.sigs[s];
+    const LenPlan& lp = A.lens[d.len_id];
+    const int tiles = lp.N1 / lp.TC;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < tiles; ++t) {
+        const double* c = A.chk + ((int64_t)d.p1_off + t) * 4;
+        v[0] += c[0];
+        v[1] += c[1];
+        v[2] += c[2];
+        v[3] += c[3];
+    }
+    const int64_t m = S->m;
+    const double sd_m = v[1] > 0.0 ? sqrt(v[0] / v[1]) : 0.0;
+    const double sd_p = (m == 1) ? INFINITY : (v[3] > 0.0 ? sqrt(v[2] / v[3]) : 0.0);
+    const bool okm = sd_m <= A.delta, okp = sd_p <= A.delta;
+    S->chk = 0;
+    if ((okm && !okp) || (!okm && m >= A.max_inner)) {
+        const uint32_t flags = okm ? 0u : (uint32_t)FIF_IMF_CAP;
+        S->sd = sd_m;
+        S->sd_prev = sd_p;
+        S->flags |= (int32_t)flags;
+        if (A.info) {
+            fif_imf_info* I = A.info + (int64_t)s * A.max_imfs + A.t;
+            I->sd = sd_m;
+            I->sd_prev = sd_p;
+            I->flags = flags;
+        }
+    } else {
+        S->redo = 1;
     }
 }
 
@@ -1611,6 +1720,9 @@ __global__ void k_reset_state(SigState* __restrict__ st, int B)
     z.status = 0;
     z.final_buf = 0;
     z.flags = 0;
+    z.fpeak = 1;
+    z.chk = 0;
+    z.redo = 0;
     st[s] = z;
 }
 

@@ -57,7 +57,7 @@ struct SigDesc {
     int32_t bs;                    // multi-workgroup scan state index, -1 if not used
     int32_t bt_off;                // first tile of its multi-workgroup scan partials
     int32_t n_btiles;              // tiles of its multi-workgroup scan
-    int32_t pad;
+    int32_t p1_off;                // its first pass-1 work item (deferred FP64 check partials)
 };
 
 // Multi-workgroup search for m (signals with more than one workgroup's bins).
@@ -101,6 +101,10 @@ struct SigState {
     int32_t status;                // 0 or FIF_ERR_NONFINITE
     int32_t final_buf;             // spectrum buffer holding the final residual
     int32_t flags;
+    // deferred FP64 check of m: chk = 1 while pass 1 accumulates the FP64
+    // stop-test sums of this step; redo = 1 when the check failed and the
+    // step is being recomputed (search, pass 1) before pass 2
+    int32_t chk, redo;
 };
 
 // Work item of the FFT kernels: signal and tile index.

@@ -336,3 +336,36 @@ def test_long_signal_full_size():
     for j in range(upto):
         a = ref.imfs[j]
         assert np.linalg.norm(a - imfs[j]) <= 1e-5 * np.linalg.norm(a), j
+
+
+@pytest.mark.parametrize("shift", [1, -1])
+def test_deferred_check_redo_path(shift, monkeypatch):
+    """The FP64 check of m for four-step signals runs inside pass 1; when it
+    fails the step is redone (exact search, pass 1 again). A host-side hook
+    shifts every deferred estimate so that every check fails: decisions must
+    equal the unshifted run's and the oracle's, and every IMF is flagged as
+    refined."""
+    lengths = [65536, 65536, 16384, 4096, 12000]
+    sigs = [siggen.chirps(i).astype(np.float32) if N == 65536 else _signal(N, 900 + i).astype(np.float32)
+            for i, N in enumerate(lengths)]
+    print("case deferred check shift=%d" % shift, flush=True)
+    plan0, packed, ref = _run_batch(lengths, sigs, 1e-3, 6, torch.float32)
+    monkeypatch.setenv("FIF_DEBUG_MT_SHIFT", str(shift))
+    plan1, _, out = _run_batch(lengths, sigs, 1e-3, 6, torch.float32)
+    i0, i1 = ref.info(), out.info()
+    n0, n1 = ref.n_imfs.cpu().numpy(), out.n_imfs.cpu().numpy()
+    assert np.array_equal(n0, n1)
+    for key in ("k", "L", "m"):
+        assert np.array_equal(i0[key], i1[key]), key
+    for b, N in enumerate(lengths):
+        four_step = N > 8192
+        valid = np.arange(6) < n1[b]
+        if four_step:
+            assert np.all(i1["flags"][b][valid] & fif.IMF_REFINED)
+        a = ref.imfs_of(b).double()
+        c = out.imfs_of(b).double()
+        assert float((a - c).norm()) <= 1e-6 * float(a.norm())
+    refs = oracle_many([s.astype(np.float64) for s in sigs[:2]], 1e-3, 6)
+    for b, r in enumerate(refs):
+        _check(r, sigs[b].astype(np.float64), out.imfs_of(b).cpu().numpy().astype(np.float64),
+               out.remainder_of(b).cpu().numpy().astype(np.float64), i1[b], int(n1[b]), 1e-3, False)
