@@ -183,9 +183,11 @@ fif_status set_lds_limits()
         set((const void*)k_single<MODE_REMAINDER, double, double>);
         set((const void*)k_pass1<MODE_FORWARD, float>);
         set((const void*)k_pass1<MODE_STEP, float>);
+        set((const void*)k_pass1<MODE_STEP, float, true>);
         set((const void*)k_pass1<MODE_REMAINDER, float>);
         set((const void*)k_pass1<MODE_FORWARD, double>);
         set((const void*)k_pass1<MODE_STEP, double>);
+        set((const void*)k_pass1<MODE_STEP, double, true>);
         set((const void*)k_pass1<MODE_REMAINDER, double>);
         set((const void*)k_pass2<MODE_FORWARD, float, float>);
         set((const void*)k_pass2<MODE_STEP, float, float>);
@@ -685,7 +687,6 @@ Bound bind(const fif_plan* p, void* ws, double delta, fif_imf_info* info)
     A.itab = p->d_itab;
     A.gamma = p->opt.gamma;
     A.chk = (double*)(w + p->ws_chk);
-    A.redo_only = 0;
     A.spec0 = (double2*)(w + p->ws_spec0);
     A.spec1 = (double2*)(w + p->ws_spec1);
     A.inter = (double2*)(w + p->ws_inter);
@@ -884,9 +885,7 @@ void launch_step(const fif_plan* p, Bound& b, int t, const T* x, T* imfs, void* 
             k_verify<<<(unsigned)((g.ssmall.count + 63) / 64), 64, 0, s>>>(V, g.ssmall.count);
             V.redo_only = 1;
             launch_k_scan<true>(0, g.ssmall.count, sizeof(float) * kScanBinsPerThread * kScanThreads, s, V);
-            StepArgs R = A;
-            R.redo_only = 1;
-            k_pass1<MODE_STEP, T><<<(unsigned)g.p1.count, kFftThreads, p->lds_p1, s>>>(R, x);
+            k_pass1<MODE_STEP, T, true><<<(unsigned)g.p1.count, kFftThreads, p->lds_p1, s>>>(A, x);
         }
         A.work = p->d_p2 + g.p2.begin;
         Timed tm(p, "pass2_step", s);

@@ -15,6 +15,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <stddef.h>
 
 #include "../../include/fif.h"
 #include "fif_fft.hpp"
@@ -52,6 +53,39 @@ __device__ __forceinline__ void run_push(RunState& r, double v)
         }
         r.last = v;
     }
+}
+
+// Word-wise copies of a RunState to and from memory: aggregate copies of
+// this struct (three words, the last holding four bytes) were lowered through
+// private scratch memory.
+static_assert(sizeof(RunState) == 24 && offsetof(RunState, cnt) == 16 && offsetof(RunState, fs) == 20 &&
+                  offsetof(RunState, ls) == 21 && offsetof(RunState, empty) == 22 &&
+                  offsetof(RunState, nonfinite) == 23,
+              "RunState layout");
+__device__ __forceinline__ RunState run_load(const RunState* p)
+{
+    const long long* q = reinterpret_cast<const long long*>(p);
+    const long long w0 = q[0], w1 = q[1], w2 = q[2];
+    RunState r;
+    r.first = __longlong_as_double(w0);
+    r.last = __longlong_as_double(w1);
+    r.cnt = (int)(w2 & 0xffffffffLL);
+    const int b = (int)(w2 >> 32);
+    r.fs = (int8_t)(b & 0xff);
+    r.ls = (int8_t)((b >> 8) & 0xff);
+    r.empty = (int8_t)((b >> 16) & 0xff);
+    r.nonfinite = (int8_t)((b >> 24) & 0xff);
+    return r;
+}
+
+__device__ __forceinline__ void run_store(RunState* p, const RunState& r)
+{
+    long long* q = reinterpret_cast<long long*>(p);
+    const int b = (int)(uint8_t)r.fs | ((int)(uint8_t)r.ls << 8) | ((int)(uint8_t)r.empty << 16) |
+                  ((int)(uint8_t)r.nonfinite << 24);
+    q[0] = __double_as_longlong(r.first);
+    q[1] = __double_as_longlong(r.last);
+    q[2] = (long long)(unsigned int)r.cnt | ((long long)b << 32);
 }
 
 // a then b
@@ -163,11 +197,11 @@ __device__ __forceinline__ RunState block_run_reduce(RunState r, RunState* sh)
     run_step<8>(r, lane);
     run_step<16>(r, lane);
     const RunState upper = run_readlane(r, 32);
-    if (lane == 0) sh[wave] = run_combine(r, upper);
+    if (lane == 0) run_store(sh + wave, run_combine(r, upper));
     __syncthreads();
     RunState tot = run_empty();
     if (threadIdx.x == 0) {
-        for (int w = 0; w < NW; ++w) tot = run_combine(tot, sh[w]);
+        for (int w = 0; w < NW; ++w) tot = run_combine(tot, run_load(sh + w));
     }
     __syncthreads();
     return tot;
@@ -451,7 +485,6 @@ struct StepArgs {
     const int32_t* itab;   // storage position <-> bin maps
     double gamma;          // > 0: thresholded IMF
     double* chk;           // deferred FP64 check: 4 partial sums per pass-1 work item
-    int redo_only;         // 1: only signals whose deferred check failed
     double2* spec0;
     double2* spec1;
     double2* inter;
@@ -680,7 +713,9 @@ __global__ void k_fill_specmap(const LenPlan* __restrict__ lpp, int32_t* __restr
 // TC x N2 block (row r', slot s at t*TC*N2 + r'*TC + s) as one run; pass 2
 // gathers, for its TR rows, a TR x TC run from every pass-1 tile.
 
-template <int MODE, typename InT>
+// REDO: the pass that recomputes only the signals whose deferred check
+// failed (its own instantiation, so profiles tell it apart).
+template <int MODE, typename InT, bool REDO = false>
 __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __restrict__ x)
 {
     extern __shared__ double2 lds[];
@@ -692,7 +727,7 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
     const int N1 = lp.N1, N2 = lp.N2, TC = lp.TC;
     SigState* S = A.st + w.sig;
     if (MODE == MODE_STEP && !S->active) return;
-    if (MODE == MODE_STEP && A.redo_only && !S->redo) return;
+    if (REDO && !S->redo) return;
     if (MODE == MODE_REMAINDER && S->status != 0) return;
     const int total = TC * N2;
     const FastDiv ftc = fastdiv(TC);
@@ -1048,7 +1083,7 @@ __device__ __forceinline__ void scan_prologue(const ScanArgs& A, int s, const Si
         const int chunk = (n + T - 1) / T;
         const int a = tid * chunk, b = min(n, a + chunk);
         RunState r = run_empty();
-        for (int i = a; i < b; ++i) r = run_combine(r, P[i]);
+        for (int i = a; i < b; ++i) r = run_combine(r, run_load(P + i));
         r = block_run_reduce<T>(r, shr);
         if (tid == 0) {
             const double mn = dval(S->kmin), mx = dval(S->kmax);
