@@ -26,7 +26,16 @@ Variants beyond the plain method (each off by default):
   - mask_rule=2: the spectral-peak mask length of Section 2 ("highest
     frequency peak" of the spectrum), read as L = ceil(N / f), f the highest
     bin 1 <= f <= N/2 whose power is >= peak_rho times the strongest
-    non-constant bin's (a pure tone at f cycles then gets the L of rule 0).
+    non-constant bin's (a pure tone at f cycles then gets the L of rule 0);
+  - window=shape: another window than the triangle of equation 271.  Section
+    4 only needs W's eigenvalues, the DFT of its first column (equation
+    "Lambdas"), which can be tabulated for any filter.  Read here as: h, the
+    non-negative samples `shape` (at x = i/K, i = 0..K) linearly
+    interpolated at x = |q|/L for |q| <= L - 1; the window is h convolved
+    with itself, divided by (sum h)^2 so that it sums to 1 (for shape
+    [1, 0], h is the triangle and the window is the default one); its taps
+    are folded modulo N into the circulant's first column.  The window is
+    symmetric and its DFT is (DFT h)^2, so every eigenvalue lies in [0, 1].
 """
 from __future__ import annotations
 
@@ -57,6 +66,38 @@ def eigenvalues_closed(N: int, L: int) -> np.ndarray:
     nz = p != 0
     q = np.sin(np.pi * t[nz] / N) / (L * np.sin(np.pi * u[nz] / N))
     lam[nz] = q ** 4
+    return lam
+
+
+def shape_taps(L: int, shape) -> np.ndarray:
+    """h_q for q = -(L-1) .. L-1 (unnormalised): the shape's samples at
+    x_i = i/K, i = 0..K, linearly interpolated at x = |q|/L; the position
+    |q| K / L is split exactly into an integer part and a remainder."""
+    shape = np.asarray(shape, dtype=np.float64)
+    K = shape.size - 1
+    q = np.arange(-(L - 1), L, dtype=np.int64)
+    u = np.abs(q) * K
+    i = u // L
+    rr = u % L
+    return shape[i] + (shape[i + 1] - shape[i]) * (rr.astype(np.float64) / float(L))
+
+
+def window_column_shape(N: int, L: int, shape) -> np.ndarray:
+    """First column of the circulant W of a sampled window shape: the taps of
+    h * h / (sum h)^2 (q = -(2L-2) .. 2L-2) folded modulo N."""
+    h = shape_taps(L, shape)
+    w = np.convolve(h, h) / float(np.sum(h)) ** 2
+    q = np.arange(-(2 * L - 2), 2 * L - 1, dtype=np.int64)
+    c = np.zeros(N)
+    np.add.at(c, q % N, w)
+    return c
+
+
+def eigenvalues_shape(N: int, L: int, shape) -> np.ndarray:
+    """lambda_p, p = 0..N-1, of a sampled window shape: the DFT of the folded
+    column (equation "Lambdas"); lambda_0 = 1 (the column sums to 1)."""
+    lam = np.fft.fft(window_column_shape(N, L, shape)).real
+    lam[0] = 1.0
     return lam
 
 
@@ -114,7 +155,10 @@ def peak_frequency(R, rho: float) -> int:
 
 def decompose(s, delta: float, max_imfs: int, *, mask_rule: int = 0, nu: float = 1.6,
               max_inner: int = 1_000_000, floor_tau: float = 1e-9, stop: str = "sd",
-              gamma: float = 0.0, peak_rho: float = 0.1, search: str = "linear") -> dif.Decomposition:
+              gamma: float = 0.0, peak_rho: float = 0.1, search: str = "linear",
+              window=None) -> dif.Decomposition:
+    if window is not None and stop == "apriori":
+        raise ValueError("the a-priori N0 counts the triangle window's zero eigenvalues")
     s = np.ascontiguousarray(np.asarray(s, dtype=np.float64))
     N = s.size
     r = s.copy()
@@ -138,7 +182,7 @@ def decompose(s, delta: float, max_imfs: int, *, mask_rule: int = 0, nu: float =
             L = max(1, -(-N // peak_frequency(R, peak_rho)))
         else:
             L = dif.mask_length(N, k, mask_rule, nu)
-        lam = eigenvalues_closed(N, L)
+        lam = eigenvalues_closed(N, L) if window is None else eigenvalues_shape(N, L, window)
         P = (R.real * R.real + R.imag * R.imag)
         mu = (1.0 - lam) ** 2
         lam2 = lam * lam
