@@ -21,6 +21,9 @@ Workloads (synthetic, seeded; see siggen):
           proposal network was trained on), delta 1e-3, 8 IMFs, with the
           trained network proposing m; the same batch without proposals is
           timed after it and reported beside
+  window  the chirps batch with a sampled window shape (raised cosine,
+          33 samples) instead of the triangle: every outer step tabulates
+          the eigenvalues from a forward transform of the folded taps
 """
 from __future__ import annotations
 
@@ -46,8 +49,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+RAISED_COS_33 = [0.5 * (1.0 + float(np.cos(np.pi * i / 32))) for i in range(33)]
+
+
 def workload(name: str):
     import siggen
+    if name == "window":
+        B, N = 1024, 65536
+        return dict(workload="window-raised-cosine-1024x65536", lengths=[N] * B, delta=1e-3, max_imfs=12,
+                    io="f32", window=RAISED_COS_33, make=lambda: [siggen.chirps(i) for i in range(B)])
     if name in ("chirps", "plain"):
         B, N = 1024, 65536
         return dict(workload="chirps-1024x65536", lengths=[N] * B, delta=1e-3, max_imfs=12, io="f32",
@@ -117,21 +127,34 @@ def algorithmic_bytes(kind: str, lengths, n_imfs, max_imfs: int, esize: int) -> 
         return float(np.sum(Ls)) * esize
     if kind == "single_rem":
         return float(np.sum(sp)) + float(np.sum(Ls)) * esize
+    if kind == "window":
+        # write the folded taps, transform them (read), write the eigenvalue table
+        L_all, sp_all = L, spec
+        return sum(float(np.sum(8.0 * L_all[n > t] * 2 + sp_all[n > t] / 2)) for t in range(max_imfs))
     return 0.0                                              # bookkeeping / implementation-only kernels
 
 
-def cpu_baseline(sigs, delta, max_imfs, want: int, budget_s: float, threads: int):
+def cpu_baseline(sigs, delta, max_imfs, want: int, budget_s: float, threads: int, window=None):
     """The oracle, one signal per host thread (the C oracle releases the GIL),
-    over rounds of `threads` signals until `want` signals or the budget."""
+    over rounds of `threads` signals until `want` signals or the budget.  A
+    sampled window shape runs the FP64 spectral oracle (numpy) instead, the
+    time-domain one having only the triangle."""
     from concurrent.futures import ThreadPoolExecutor
     from oracle import dif
+    from oracle import fif_spectral
+
+    def one(s):
+        s = np.asarray(s, dtype=np.float64)
+        if window is not None:
+            return fif_spectral.decompose(s, delta, max_imfs, window=window)
+        return dif.decompose(s, delta, max_imfs)
     t0 = time.perf_counter()
     done = 0
     samples = 0
     with ThreadPoolExecutor(max_workers=threads) as ex:
         while done < min(want, len(sigs)) and time.perf_counter() - t0 < budget_s:
             batch = sigs[done:min(want, len(sigs), done + threads)]
-            list(ex.map(lambda s: dif.decompose(np.asarray(s, dtype=np.float64), delta, max_imfs), batch))
+            list(ex.map(one, batch))
             done += len(batch)
             samples += sum(len(s) for s in batch)
     el = time.perf_counter() - t0
@@ -143,7 +166,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="chirps", choices=["chirps", "uneven", "long", "tones3", "plain", "learned"])
+    ap.add_argument("--workload", default="chirps", choices=["chirps", "uneven", "long", "tones3", "plain", "learned", "window"])
     ap.add_argument("--model", default=MODEL_FILE, help="proposal network file (learned workload)")
     ap.add_argument("--cpu-signals", type=int, default=8, help="signals the CPU oracle decomposes at most")
     ap.add_argument("--cpu-threads", type=int, default=1,
@@ -203,7 +226,7 @@ def main():
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
     else:
-        plan = fif.Plan(lengths, J)
+        plan = fif.Plan(lengths, J, fif.Options(window=W.get("window")))
         out = plan.alloc_outputs(dt)
         model = None
         if args.workload == "learned":
@@ -303,7 +326,8 @@ def main():
                    "launch": "hip graph replay" if (args.graph and args.workload != "plain")
                    else "stream",
                    "form": "plain single-signal" if args.workload == "plain" else
-                   ("batched, learned proposal of m" if args.workload == "learned" else "batched")},
+                   ("batched, learned proposal of m" if args.workload == "learned" else
+                    ("batched, sampled window shape" if args.workload == "window" else "batched"))},
     }
     if args.workload not in ("plain",) and extra:
         res["config"].update(extra)
@@ -311,12 +335,14 @@ def main():
         res["roofline"] = roofline
     if not args.no_cpu_baseline:
         threads = max(1, args.cpu_threads)
-        done, samples, cel = cpu_baseline(sigs, delta, J, args.cpu_signals, args.cpu_budget, threads)
+        done, samples, cel = cpu_baseline(sigs, delta, J, args.cpu_signals, args.cpu_budget, threads,
+                                          W.get("window"))
         res["cpu_baseline"] = {
             "value": samples / cel, "unit": "samples/s", "cores": threads, "kind": "oracle",
             "sample": "first %d of %d signals of the same workload, full decomposition by the FP64 "
-                      "time-domain oracle (C), one signal per thread, %d threads, %.1f s" % (
-                          done, len(lengths), threads, cel)}
+                      "%s oracle, one signal per thread, %d threads, %.1f s" % (
+                          done, len(lengths), "spectral (numpy)" if W.get("window") else "time-domain (C)",
+                          threads, cel)}
     print(json.dumps(res), flush=True)
 
 

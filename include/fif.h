@@ -71,7 +71,9 @@ typedef enum {
 
 typedef enum {
     /* eq. "triangular" triangle of half-support L, convolved with itself */
-    FIF_WINDOW_TRI2 = 0
+    FIF_WINDOW_TRI2 = 0,
+    /* the sampled shape given in fif_options.window (see there) */
+    FIF_WINDOW_SAMPLED = 1
 } fif_window;
 
 /* per-IMF flags */
@@ -106,6 +108,24 @@ typedef struct {
                             (1 - lambda)^m >= 1 - gamma go whole into the IMF;
                             0 (default): off; must be < 1 */
     double peak_rho;     /* mask_rule 2 fraction, in (0, 1], default 0.1 */
+    const double* window;/* HOST array of window_points >= 2 samples of a window
+                            shape on [0, 1] (x_i = i / (window_points - 1)), or
+                            NULL (default): the triangle of equation 271 with the
+                            closed-form eigenvalues of equation "eig2".  Section 4
+                            needs only W's eigenvalues, the DFT of its first
+                            column (equation "Lambdas"), so any shape can be
+                            tabulated: h_q = the samples linearly interpolated at
+                            x = |q|/L, |q| <= L-1; the window is h convolved with
+                            itself over (sum h)^2, folded modulo N; each outer
+                            step then computes lambda_j = (DFT(h)_j / sum h)^2
+                            for every active signal (one extra FP64 transform
+                            per step).  Samples must be finite and >= 0, the
+                            first > 0; at most 65537 of them; copied at plan
+                            creation.  Not with stop_mode 2 (its N0 counts the
+                            triangle's zero eigenvalues).  Shape {1, 0} is the
+                            triangle itself. */
+    int32_t window_points;
+    int32_t reserved;
 } fif_options;
 
 typedef struct {

@@ -35,7 +35,13 @@ Variants beyond the plain method (each off by default):
     with itself, divided by (sum h)^2 so that it sums to 1 (for shape
     [1, 0], h is the triangle and the window is the default one); its taps
     are folded modulo N into the circulant's first column.  The window is
-    symmetric and its DFT is (DFT h)^2, so every eigenvalue lies in [0, 1].
+    symmetric and its DFT is (DFT h)^2 (convolution theorem), so every
+    eigenvalue lies in [0, 1]; they are computed in that form, as
+    (H_j / H_0)^2 with H the DFT of the folded h.  Reading where the paper is
+    silent: |H_j / H_0| < 1e-13 is taken as an exact zero (an FP64 FFT
+    resolves H only to ~1e-15, so the exact zeros a window spectrum can have,
+    such as a box's, would otherwise come out as rounding noise whose size
+    decides how the SD of later steps ends).
 """
 from __future__ import annotations
 
@@ -93,10 +99,21 @@ def window_column_shape(N: int, L: int, shape) -> np.ndarray:
     return c
 
 
+# |H_j / H_0| below this is an exact zero of the window spectrum
+WINDOW_ZERO = 1e-13
+
+
 def eigenvalues_shape(N: int, L: int, shape) -> np.ndarray:
-    """lambda_p, p = 0..N-1, of a sampled window shape: the DFT of the folded
-    column (equation "Lambdas"); lambda_0 = 1 (the column sums to 1)."""
-    lam = np.fft.fft(window_column_shape(N, L, shape)).real
+    """lambda_p, p = 0..N-1, of a sampled window shape (equation "Lambdas"
+    for the column of window_column_shape, by the convolution theorem):
+    (H_p / H_0)^2 with H the DFT of the folded taps h, H_0 = sum h; values of
+    |H_p / H_0| below WINDOW_ZERO are exact zeros; lambda_0 = 1."""
+    h = shape_taps(L, shape)
+    q = np.arange(-(L - 1), L, dtype=np.int64)
+    f = np.zeros(N)
+    np.add.at(f, q % N, h)
+    H = np.fft.fft(f).real / float(np.sum(h))
+    lam = np.where(np.abs(H) < WINDOW_ZERO, 0.0, np.minimum(H * H, 1.0))
     lam[0] = 1.0
     return lam
 

@@ -52,10 +52,12 @@ class Decomposition:
 
 
 def decompose(signal, delta: float, max_imfs: int, options: Options | None = None,
-              window: int = 0) -> Decomposition:
+              window: int | None = None) -> Decomposition:
     """Plain single-signal form (fif_decompose / fif_decompose_f64).
 
     signal: 1-D contiguous torch tensor on the current GPU, float32 or float64.
+    window: fif_window value; by default FIF_WINDOW_SAMPLED when the options
+    carry window samples, else FIF_WINDOW_TRI2.
     """
     torch = _torch()
     lib = load()
@@ -69,7 +71,10 @@ def decompose(signal, delta: float, max_imfs: int, options: Options | None = Non
     rem = torch.empty(N, dtype=signal.dtype, device=dev)
     n = torch.zeros(1, dtype=torch.int32, device=dev)
     info = torch.zeros(max(max_imfs, 1) * IMF_INFO_DTYPE.itemsize, dtype=torch.uint8, device=dev)
-    opt = (options or Options()).c()
+    options = options or Options()
+    if window is None:
+        window = 1 if options.window is not None else 0
+    opt = options.c()
     fn = lib.fif_decompose if signal.dtype == torch.float32 else lib.fif_decompose_f64
     with torch.cuda.device(dev):
         st = fn(_ptr(signal), N, window, float(delta), int(max_imfs), _ptr(imfs), _ptr(rem), _ptr(n),

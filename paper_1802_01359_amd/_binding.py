@@ -55,7 +55,8 @@ class FifError(RuntimeError):
 class _Options(ctypes.Structure):
     _fields_ = [("mask_rule", ctypes.c_int32), ("stop_mode", ctypes.c_int32), ("nu", ctypes.c_double),
                 ("max_inner", ctypes.c_int64), ("floor_tau", ctypes.c_double), ("gamma", ctypes.c_double),
-                ("peak_rho", ctypes.c_double)]
+                ("peak_rho", ctypes.c_double), ("window", ctypes.c_void_p), ("window_points", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class KernelTime(ctypes.Structure):
@@ -76,10 +77,17 @@ class Options:
     stop_mode: int = 0          # 0 SD <= delta, 1 ||s_{m+1}-s_m|| < delta, 2 a-priori N0
     gamma: float = 0.0          # > 0: thresholded IMF
     peak_rho: float = 0.1
+    window: object = None       # samples of a window shape on [0, 1]; None: the triangle
 
     def c(self) -> _Options:
-        return _Options(self.mask_rule, self.stop_mode, self.nu, self.max_inner, self.floor_tau, self.gamma,
-                        self.peak_rho)
+        o = _Options(self.mask_rule, self.stop_mode, self.nu, self.max_inner, self.floor_tau, self.gamma,
+                     self.peak_rho, None, 0, 0)
+        if self.window is not None:
+            w = np.ascontiguousarray(np.asarray(self.window, dtype=np.float64).ravel())
+            o.window = w.ctypes.data
+            o.window_points = w.size
+            o._keep = w             # the library copies the samples during the call
+        return o
 
 
 _lib = None

@@ -136,6 +136,11 @@ struct fif_plan {
     // workspace layout (byte offsets)
     size_t ws_state = 0, ws_spec0 = 0, ws_spec1 = 0, ws_inter = 0, ws_parts = 0, ws_psum = 0, ws_gscr = 0,
            ws_bigs = 0, ws_bpart = 0, ws_resid = 0, ws_feat = 0, ws_prop = 0, ws_chk = 0, ws_total = 0;
+    // sampled window shape: its samples (in the FP64 table at wshape_off),
+    // and the workspace of the per-step eigenvalue tables
+    std::vector<double> wshape;
+    int64_t wshape_off = 0;
+    size_t ws_taps = 0, ws_lam = 0, ws_wsum = 0;
     int32_t mt_shift = 0;           // test hook (FIF_DEBUG_MT_SHIFT): perturbs the deferred estimate
     // learned proposal of m, and recording of the network inputs
     fif_model* model = nullptr;
@@ -181,6 +186,9 @@ fif_status set_lds_limits()
         set((const void*)k_single<MODE_FORWARD, double, double>);
         set((const void*)k_single<MODE_STEP, double, double>);
         set((const void*)k_single<MODE_REMAINDER, double, double>);
+        set((const void*)k_single<MODE_WINDOW, double, double>);
+        set((const void*)k_pass1<MODE_WINDOW, double>);
+        set((const void*)k_pass2<MODE_WINDOW, double, double>);
         set((const void*)k_pass1<MODE_FORWARD, float>);
         set((const void*)k_pass1<MODE_STEP, float>);
         set((const void*)k_pass1<MODE_STEP, float, true>);
@@ -219,6 +227,19 @@ fif_status validate_opts(const fif_options& o)
         return fail(FIF_ERR_INVALID_ARG, "max_inner must be in [1, 2^40]");
     if (!(o.floor_tau >= 0.0 && std::isfinite(o.floor_tau)))
         return fail(FIF_ERR_INVALID_ARG, "floor_tau must be finite and >= 0");
+    if (o.window) {
+        if (o.window_points < 2 || o.window_points > kMaxWindowPoints)
+            return fail(FIF_ERR_INVALID_ARG, "window_points must be in [2, %d]", kMaxWindowPoints);
+        for (int i = 0; i < o.window_points; ++i)
+            if (!(o.window[i] >= 0.0 && std::isfinite(o.window[i])))
+                return fail(FIF_ERR_INVALID_ARG, "window sample %d must be finite and >= 0", i);
+        if (!(o.window[0] > 0.0)) return fail(FIF_ERR_INVALID_ARG, "the first window sample must be > 0");
+        if (o.stop_mode == 2)
+            return fail(FIF_ERR_INVALID_ARG, "stop_mode 2 counts the triangle window's zero eigenvalues: "
+                                             "not with a sampled window");
+    } else if (o.window_points != 0) {
+        return fail(FIF_ERR_INVALID_ARG, "window_points given without window samples");
+    }
     return FIF_OK;
 }
 
@@ -290,6 +311,9 @@ void fif_options_default(fif_options* opt)
     opt->floor_tau = 1e-9;
     opt->gamma = 0.0;
     opt->peak_rho = 0.1;
+    opt->window = nullptr;
+    opt->window_points = 0;
+    opt->reserved = 0;
 }
 
 const char* fif_last_error(void) { return g_err.c_str(); }
@@ -327,7 +351,8 @@ fif_status fif_plan_create(fif_plan** out, const int64_t* lengths, int32_t B, in
     p->max_imfs = max_imfs;
     p->opt = opt;
     p->lengths.assign(lengths, lengths + B);
-
+    if (opt.window) p->wshape.assign(opt.window, opt.window + opt.window_points);
+    p->opt.window = nullptr;    // the caller's array is not kept
     std::map<int64_t, int32_t> len_id;
     for (int32_t b = 0; b < B; ++b) {
         const int64_t N = lengths[b];
@@ -392,6 +417,8 @@ fif_status fif_plan_create(fif_plan** out, const int64_t* lengths, int32_t B, in
             ccount += nhi;
         }
     }
+    p->wshape_off = dcount;
+    dcount += (int64_t)p->wshape.size();
 
     // signals, work lists, workspace sizes
     int64_t off = 0, spec = 0, inter = 0, inter_max = 0, gscr = 0, resid = 0;
@@ -531,6 +558,14 @@ fif_status fif_plan_create(fif_plan** out, const int64_t* lengths, int32_t B, in
     ws += sizeof(int64_t) * (size_t)B;
     p->ws_chk = ws = align_up(ws, 256);
     ws += sizeof(double) * 4 * (p->w_p1.size() + 1);
+    if (!p->wshape.empty()) {
+        p->ws_taps = ws = align_up(ws, 256);
+        ws += sizeof(double) * (size_t)off;
+        p->ws_lam = ws = align_up(ws, 256);
+        ws += sizeof(double) * (size_t)spec;
+        p->ws_wsum = ws = align_up(ws, 256);
+        ws += sizeof(double) * (size_t)B;
+    }
     {
         const char* env = getenv("FIF_DEBUG_MT_SHIFT");
         p->mt_shift = env ? atoi(env) : 0;
@@ -598,6 +633,9 @@ fif_status fif_plan_create(fif_plan** out, const int64_t* lengths, int32_t B, in
         if (r.count <= 0) continue;
         k_fill_roots<<<(unsigned)((r.count + 255) / 256), 256>>>(p->d_ctab + r.off, r.den, r.count, r.stride);
     }
+    if (!p->wshape.empty())
+        HIP_TRY(hipMemcpy(p->d_dtab + p->wshape_off, p->wshape.data(), sizeof(double) * p->wshape.size(),
+                          hipMemcpyHostToDevice));
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipDeviceSynchronize());
     *out = p.release();
@@ -687,6 +725,8 @@ Bound bind(const fif_plan* p, void* ws, double delta, fif_imf_info* info)
     A.itab = p->d_itab;
     A.gamma = p->opt.gamma;
     A.chk = (double*)(w + p->ws_chk);
+    A.lam = p->wshape.empty() ? nullptr : (double*)(w + p->ws_lam);
+    A.wsum = p->wshape.empty() ? nullptr : (double*)(w + p->ws_wsum);
     A.spec0 = (double2*)(w + p->ws_spec0);
     A.spec1 = (double2*)(w + p->ws_spec1);
     A.inter = (double2*)(w + p->ws_inter);
@@ -719,6 +759,7 @@ Bound bind(const fif_plan* p, void* ws, double delta, fif_imf_info* info)
     S.floor_tau = p->opt.floor_tau;
     S.stop_mode = p->opt.stop_mode;
     S.chk = A.chk;
+    S.lam = A.lam;
     S.defer = p->opt.stop_mode == 0 ? 1 : 0;
     S.redo_only = 0;
     S.mt_shift = p->mt_shift;
@@ -767,6 +808,30 @@ void launch_k_scan(int mode, int n, size_t lds, hipStream_t s, const ScanArgs& S
         k_scan<kScanBinsPerThread, PRE, 0><<<(unsigned)n, kScanThreads, lds, s>>>(S);
 }
 
+// Eigenvalue tables of a sampled window shape for the active signals of one
+// group, at the L the step start just fixed: folded taps, their forward
+// transform, lambda_j = (H_j / H_0)^2.
+void launch_window(const fif_plan* p, Bound& b, void* ws, hipStream_t s, const fif_plan::Group& g)
+{
+    Timed tm(p, "window", s);
+    double* taps = (double*)((char*)ws + p->ws_taps);
+    k_window_taps<<<(unsigned)(g.s1 - g.s0), kFftThreads, 0, s>>>(p->d_sigs, b.state, p->d_dtab + p->wshape_off,
+                                                                  (int)p->wshape.size() - 1, taps, b.sa.wsum, g.s0);
+    StepArgs A = b.sa;
+    if (g.single.count) {
+        A.work = p->d_single + g.single.begin;
+        k_single<MODE_WINDOW, double, double><<<(unsigned)g.single.count, kFftThreads, p->lds_single, s>>>(
+            A, taps, nullptr, nullptr);
+    }
+    if (g.p1.count) {
+        A.work = p->d_p1 + g.p1.begin;
+        k_pass1<MODE_WINDOW, double><<<(unsigned)g.p1.count, kFftThreads, p->lds_p1, s>>>(A, taps);
+        A.work = p->d_p2 + g.p2.begin;
+        k_pass2<MODE_WINDOW, double, double><<<(unsigned)g.p2.count, kFftThreads, p->lds_p2, s>>>(A, taps, nullptr,
+                                                                                                   nullptr);
+    }
+}
+
 // Search for m of every active signal.  With a proposal model or feature
 // recording the step starts (count combine, stop rules, L) run first, then
 // the features, the network and the proposals, then the searches.
@@ -774,7 +839,7 @@ void launch_scan(const fif_plan* p, Bound& b, int t, void* ws, hipStream_t s, co
 {
     ScanArgs S = b.sc;
     S.t = t;
-    const bool split = p->model || p->rec;
+    const bool split = p->model || p->rec || !p->wshape.empty();
     const unsigned nb = (unsigned)g.sbig.count, nt = (unsigned)g.btile.count;
     const Work* btile = p->d_btile + g.btile.begin;
     const size_t scan_lds = sizeof(float) * kScanBinsPerThread * kScanThreads;
@@ -805,10 +870,11 @@ void launch_scan(const fif_plan* p, Bound& b, int t, void* ws, hipStream_t s, co
                 k_bscan_prep<kScanThreads><<<nb, kScanThreads, 0, s>>>(S);
             }
         }
+        if (!p->wshape.empty()) launch_window(p, b, ws, s, g);
         char* w = (char*)ws;
         uint16_t* feat = (uint16_t*)(w + p->ws_feat);
         int64_t* prop = (int64_t*)(w + p->ws_prop);
-        {
+        if (p->model || p->rec) {
             Timed tm(p, "features", s);
             FeatArgs F;
             F.sigs = p->d_sigs;
@@ -990,7 +1056,10 @@ struct SingleCache {
         void* ws = nullptr;
         SigState* host_state = nullptr;
     };
-    std::map<std::tuple<int, int64_t, int32_t, int32_t, double, int64_t, double, int32_t, double, double>, Entry> map;
+    std::map<std::tuple<int, int64_t, int32_t, int32_t, double, int64_t, double, int32_t, double, double,
+                        std::vector<double>>,
+             Entry>
+        map;
     ~SingleCache() { clear(); }
     void clear()
     {
@@ -1013,12 +1082,16 @@ fif_status single(const T* x, int64_t N, fif_window window, double delta, int32_
                   int32_t* n_imfs, fif_imf_info* info, const fif_options* opt_in, void* stream)
 {
     g_err.clear();
-    if (window != FIF_WINDOW_TRI2) return fail(FIF_ERR_INVALID_ARG, "unknown window %d", (int)window);
+    if (window != FIF_WINDOW_TRI2 && window != FIF_WINDOW_SAMPLED)
+        return fail(FIF_ERR_INVALID_ARG, "unknown window %d", (int)window);
     if (!x || !imfs || !rem || !n_imfs) return fail(FIF_ERR_INVALID_ARG, "null buffer argument");
     if (!(delta > 0.0) || !std::isfinite(delta)) return fail(FIF_ERR_INVALID_ARG, "delta must be > 0 and finite");
     fif_options opt;
     fif_options_default(&opt);
     if (opt_in) opt = *opt_in;
+    if ((window == FIF_WINDOW_SAMPLED) != (opt.window != nullptr))
+        return fail(FIF_ERR_INVALID_ARG, "FIF_WINDOW_SAMPLED goes with window samples in the options, "
+                                         "FIF_WINDOW_TRI2 without");
     fif_status vst = validate_opts(opt);
     if (vst) return vst;
     if (max_imfs < 1 || max_imfs > 4096) return fail(FIF_ERR_INVALID_ARG, "max_imfs must be in [1, 4096]");
@@ -1028,8 +1101,10 @@ fif_status single(const T* x, int64_t N, fif_window window, double delta, int32_
     HIP_TRY(hipGetDevice(&dev));
     auto& C = single_cache();
     std::lock_guard<std::mutex> lock(C.mu);
+    std::vector<double> wkey;
+    if (opt.window) wkey.assign(opt.window, opt.window + opt.window_points);
     auto key = std::make_tuple(dev, N, max_imfs, opt.mask_rule, opt.nu, opt.max_inner, opt.floor_tau, opt.stop_mode,
-                               opt.gamma, opt.peak_rho);
+                               opt.gamma, opt.peak_rho, wkey);
     auto it = C.map.find(key);
     if (it == C.map.end()) {
         SingleCache::Entry e;

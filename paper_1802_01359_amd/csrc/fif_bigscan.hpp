@@ -207,7 +207,7 @@ __device__ __forceinline__ void bscan_tile_sums(const ScanArgs& A, const SigDesc
             out[tid] = (double)s;
         }
     } else {
-        const Lam lw = make_lam(lp, A.dtab, G->L);
+        const Lam lw = make_lam(lp, A.dtab, G->L, A.lam ? A.lam + d.spec_off : nullptr);
         // position -> bin table of this length, read once (null: bin order)
         const int32_t* btab = lp.spec_perm ? A.itab + lp.bin_off : nullptr;
         const double pscale = G->pscale;
@@ -421,7 +421,7 @@ __global__ __launch_bounds__(T) void k_bscan_round(ScanArgs A, const Work* __res
         float* av = tau + nh;
         float* bv = av + nh;
         const double2* R = ((A.t & 1) ? A.spec1 : A.spec0) + d.spec_off;
-        const Lam lw = make_lam(lp, A.dtab, G->L);
+        const Lam lw = make_lam(lp, A.dtab, G->L, A.lam ? A.lam + d.spec_off : nullptr);
         // position -> bin table of this length, read once (null: bin order)
         const int32_t* btab = lp.spec_perm ? A.itab + lp.bin_off : nullptr;
         const double pscale = G->pscale;

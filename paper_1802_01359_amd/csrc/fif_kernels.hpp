@@ -311,11 +311,13 @@ struct Lam {
     double invN, invL;
     const double* sinT;   // sin(pi u/N), u <= N/2
     const double* isinT;  // 1/sin(pi u/N), 1 <= u <= N/2
+    const double* tab;    // sampled window shape: lambda_j of this step by bin, else null
 };
 
-__device__ __forceinline__ Lam make_lam(const LenPlan& lp, const double* dtab, int64_t L)
+__device__ __forceinline__ Lam make_lam(const LenPlan& lp, const double* dtab, int64_t L, const double* tab)
 {
     Lam w;
+    w.tab = tab;
     w.N = lp.N;
     w.Lmod = L % lp.N;
     w.invN = lp.invN;
@@ -331,6 +333,7 @@ __device__ __forceinline__ Lam make_lam(const LenPlan& lp, const double* dtab, i
 __device__ __forceinline__ double lambda_at(int64_t j, const Lam& w)
 {
     if (j == 0) return 1.0;
+    if (w.tab) return w.tab[j];
     int64_t t = mulmod53(w.Lmod, j, w.N, w.invN);
     if (t > w.N - t) t = w.N - t;
     const double q = w.sinT[t] * w.isinT[j] * w.invL;
@@ -471,9 +474,64 @@ __global__ __launch_bounds__(kFftThreads) void k_init_stats(const SigDesc* __res
     }
 }
 
+// ------------------------------------------------ sampled window shapes --
+
+// Folded taps of a sampled window shape for every active signal of
+// [s0, s0 + gridDim.x) at its current L: h_q = shape[i] + (shape[i+1] -
+// shape[i]) rr / L with |q| K = i L + rr (linear interpolation of the K + 1
+// samples at x = |q|/L), for |q| <= L - 1, summed into slot q mod N.  Also
+// writes the sum of the taps (H_0).  The taps are unnormalised; the
+// eigenvalue table divides by that sum.  Floors of quotients of integers
+// below 2^53 are taken in FP64, where they are exact.
+__global__ __launch_bounds__(kFftThreads) void k_window_taps(const SigDesc* __restrict__ sigs,
+                                                              const SigState* __restrict__ st,
+                                                              const double* __restrict__ shape, int K,
+                                                              double* __restrict__ taps, double* __restrict__ wsum,
+                                                              int s0)
+{
+    __shared__ double shd[kFftThreads / 64];
+    const int s = s0 + blockIdx.x;
+    if (!st[s].active) return;
+    const SigDesc d = sigs[s];
+    const int64_t N = d.N, L = st[s].L;
+    const double dN = (double)N, dL = (double)L;
+    double acc[1] = {0.0};
+    for (int64_t n = threadIdx.x; n < N; n += kFftThreads) {
+        // smallest q = n (mod N) with q >= -(L-1), then every N up to L-1
+        int64_t q = n - (int64_t)floor((double)(n + L - 1) / dN) * N;
+        double v = 0.0;
+        for (; q <= L - 1; q += N) {
+            const int64_t u = (q < 0 ? -q : q) * (int64_t)K;
+            const int64_t i = (int64_t)floor((double)u / dL);
+            const int64_t rr = u - i * L;
+            v += shape[i] + (shape[i + 1] - shape[i]) * ((double)rr / dL);
+        }
+        taps[d.off + n] = v;
+        acc[0] += v;
+    }
+    block_sum<double, kFftThreads, 1>(acc, shd);
+    if (threadIdx.x == 0) wsum[s] = acc[0];
+}
+
 // ------------------------------------------------------ transform modes --
 
-enum Mode { MODE_FORWARD = 0, MODE_STEP = 1, MODE_REMAINDER = 2 };
+// WINDOW: the forward transform of a sampled window's folded taps (FP64
+// input), written out as the eigenvalue table of this step.
+enum Mode { MODE_FORWARD = 0, MODE_STEP = 1, MODE_REMAINDER = 2, MODE_WINDOW = 3 };
+__host__ __device__ constexpr bool fwd_mode(int m) { return m == MODE_FORWARD || m == MODE_WINDOW; }
+
+// lambda_n = (H_n / H_0)^2 for bin n <= N/2 of the folded taps' transform H
+// (real up to rounding for symmetric taps), lambda_0 = 1.  |H_n / H_0|
+// below kWindowZero is an exact zero of the window spectrum: the FP64
+// transform resolves it only to ~1e-15, and the size of such rounding noise
+// would otherwise decide how the SD of later steps ends.
+constexpr double kWindowZero = 1e-13;
+__device__ __forceinline__ double window_lambda(int64_t n, double hx, double inv_sum)
+{
+    if (n == 0) return 1.0;
+    const double h = hx * inv_sum;
+    return fabs(h) < kWindowZero ? 0.0 : fmin(h * h, 1.0);
+}
 
 struct StepArgs {
     const SigDesc* sigs;
@@ -485,6 +543,8 @@ struct StepArgs {
     const int32_t* itab;   // storage position <-> bin maps
     double gamma;          // > 0: thresholded IMF
     double* chk;           // deferred FP64 check: 4 partial sums per pass-1 work item
+    double* lam;           // sampled window shape: lambda_j per signal (at spec_off), else null
+    double* wsum;          // sampled window shape: sum of each signal's taps
     double2* spec0;
     double2* spec1;
     double2* inter;
@@ -527,10 +587,17 @@ __global__ __launch_bounds__(kFftThreads) void k_single(StepArgs A, const InT* _
     const int nh = N / 2;
     SigState* S = A.st + w.sig;
 
-    if (MODE == MODE_FORWARD) {
+    if (fwd_mode(MODE)) {
+        if (MODE == MODE_WINDOW && !S->active) return;
         for (int k = threadIdx.x; k < N; k += kFftThreads) lds[k] = make_double2((double)x[d.off + k], 0.0);
         __syncthreads();
         lds_fft<false, kFftCap>(lds, lp.f1, 1, A.ctab);
+        if (MODE == MODE_WINDOW) {
+            double* lt = A.lam + d.spec_off;
+            const double inv = 1.0 / A.wsum[w.sig];
+            for (int k = threadIdx.x; k <= nh; k += kFftThreads) lt[k] = window_lambda(k, lds[k].x, inv);
+            return;
+        }
         double2* out = A.spec0 + d.spec_off;
         for (int k = threadIdx.x; k <= nh; k += kFftThreads) out[k] = lds[k];
         return;
@@ -549,7 +616,7 @@ __global__ __launch_bounds__(kFftThreads) void k_single(StepArgs A, const InT* _
     double2* Rout = spec_in(A, buf ^ 1) + d.spec_off;
     const double invN = 1.0 / (double)N;
     const int64_t L = S->L, m = S->m;
-    const Lam lw = make_lam(lp, A.dtab, L > 0 ? L : 1);
+    const Lam lw = make_lam(lp, A.dtab, L > 0 ? L : 1, A.lam ? A.lam + d.spec_off : nullptr);
     for (int j = threadIdx.x; j <= nh; j += kFftThreads) {
         const double2 v = Rin[j];
         double g = 0.0;
@@ -726,12 +793,12 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
     const int64_t N = d.N;
     const int N1 = lp.N1, N2 = lp.N2, TC = lp.TC;
     SigState* S = A.st + w.sig;
-    if (MODE == MODE_STEP && !S->active) return;
+    if ((MODE == MODE_STEP || MODE == MODE_WINDOW) && !S->active) return;
     if (REDO && !S->redo) return;
     if (MODE == MODE_REMAINDER && S->status != 0) return;
     const int total = TC * N2;
     const FastDiv ftc = fastdiv(TC);
-    if (MODE == MODE_FORWARD) {
+    if (fwd_mode(MODE)) {
         for (int f = threadIdx.x; f < total; f += kFftThreads) {
             int s;
             const int r = fdivmod(f, ftc, s);
@@ -743,7 +810,7 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
         double2* Rout = spec_in(A, buf ^ 1) + d.spec_off;
         const double invN = 1.0 / (double)N;
         const int64_t L = S->L, m = S->m;
-        const Lam lw = make_lam(lp, A.dtab, L > 0 ? L : 1);
+        const Lam lw = make_lam(lp, A.dtab, L > 0 ? L : 1, A.lam ? A.lam + d.spec_off : nullptr);
         if (lp.paired) {
             const int h = TC >> 1;
             const int owners = TC * (N2 >> 1);
@@ -844,7 +911,7 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
         }
     }
     __syncthreads();
-    if (MODE == MODE_FORWARD)
+    if (fwd_mode(MODE))
         lds_fft<false, kTileCap>(lds, lp.f1, TC, A.ctab);
     else
         lds_fft<true, kTileCap>(lds, lp.f1, TC, A.ctab);
@@ -856,8 +923,8 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
         const int64_t a = (int64_t)rp * c;
         double2 v = lds[f];
         if (a != 0) {
-            const double2 tw = (MODE == MODE_FORWARD) ? big_twiddle<false>(pr, A.ctab, a)
-                                                      : big_twiddle<true>(pr, A.ctab, a);
+            const double2 tw = fwd_mode(MODE) ? big_twiddle<false>(pr, A.ctab, a)
+                                              : big_twiddle<true>(pr, A.ctab, a);
             v = cmul(v, tw);
         }
         Y[(int64_t)w.tile * total + f] = v;
@@ -886,6 +953,7 @@ __global__ __launch_bounds__(kFftThreads) void k_pass2(StepArgs A, const InT* __
     SigState* S = A.st + w.sig;
     const int total = TR * N1;
     const FastDiv ftr = fastdiv(TR);
+    if (MODE == MODE_WINDOW && !S->active) return;
     if (MODE == MODE_STEP && w.tile == 0 && threadIdx.x == 0) S->redo = 0;   // the step is final now
     if (MODE == MODE_STEP && !S->active) {
         OutT* row = imfs + (int64_t)A.max_imfs * d.off + (int64_t)A.t * N;
@@ -938,10 +1006,22 @@ __global__ __launch_bounds__(kFftThreads) void k_pass2(StepArgs A, const InT* __
         }
     }
     __syncthreads();
-    if (MODE == MODE_FORWARD)
+    if (fwd_mode(MODE))
         lds_fft<false, kTileCap>(lds, lp.f2, TR, A.ctab);
     else
         lds_fft<true, kTileCap>(lds, lp.f2, TR, A.ctab);
+    if (MODE == MODE_WINDOW) {
+        double* lt = A.lam + d.spec_off;
+        const double inv = 1.0 / A.wsum[w.sig];
+        const int64_t nh = N / 2;
+        for (int f = threadIdx.x; f < total; f += kFftThreads) {
+            int rl;
+            const int cp = fdivmod(f, ftr, rl);
+            const int64_t n = (int64_t)N2 * cp + r0 + rl;
+            if (n <= nh) lt[n] = window_lambda(n, lds[f].x, inv);
+        }
+        return;
+    }
     if (MODE == MODE_FORWARD) {
         double2* out = A.spec0 + d.spec_off;
         const int64_t nh = N / 2;
@@ -1052,6 +1132,7 @@ struct ScanArgs {
     double floor_tau;
     int stop_mode;            // 0 SD, 1 absolute step norm, 2 a-priori N0
     double* chk;              // deferred FP64 check partials (StepArgs::chk)
+    const double* lam;        // sampled window shape: lambda_j per signal (StepArgs::lam)
     int defer;                // 1: leave the FP64 check of paired four-step signals to pass 1
     int redo_only;            // 1: only signals whose deferred check failed
     int mt_shift;             // test hook: added to the deferred FP32 estimate
@@ -1219,7 +1300,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
     if (L < 0) return;
 
     const int nh = (int)(N / 2);
-    const Lam lw = make_lam(lp, A.dtab, L);
+    const Lam lw = make_lam(lp, A.dtab, L, A.lam ? A.lam + d.spec_off : nullptr);
     const double2* R = ((A.t & 1) ? A.spec1 : A.spec0) + d.spec_off;
     const double pscale = sh_d[0];
     const double delta = A.delta;

@@ -14,6 +14,8 @@ constexpr int kScanThreads = 512;
 // Spectrum bins a scan thread keeps in registers (fast path: N <= 65536).
 constexpr int kScanBinsPerThread = 64;
 constexpr int kMaxRadices = 24;
+// Most samples of a sampled window shape.
+constexpr int kMaxWindowPoints = 65537;
 
 // Radix plan of one LDS-resident complex FFT of length n.
 struct SubFft {

@@ -31,7 +31,7 @@ def _sigs(lengths):
     return [siggen.chirps(i) if N == 65536 else _signal(N, 300 + i) for i, N in enumerate(lengths)]
 
 
-def _batch_vs_oracle(lengths, delta, max_imfs, dtype, oracle_kw, **opt):
+def _batch_vs_oracle(lengths, delta, max_imfs, dtype, oracle_kw, lam_abs=None, **opt):
     sigs = _sigs(lengths)
     if dtype == torch.float32:
         sigs = [s.astype(np.float32) for s in sigs]
@@ -47,7 +47,7 @@ def _batch_vs_oracle(lengths, delta, max_imfs, dtype, oracle_kw, **opt):
         ref = fs.decompose(s64, delta, max_imfs, **oracle_kw)
         imfs = out.imfs_of(b).cpu().numpy().astype(np.float64)
         rem = out.remainder_of(b).cpu().numpy().astype(np.float64)
-        _check(ref, s64, imfs, rem, info[b], int(n[b]), delta, dtype == torch.float64)
+        _check(ref, s64, imfs, rem, info[b], int(n[b]), delta, dtype == torch.float64, lam_abs)
     return info, n
 
 

@@ -49,6 +49,7 @@ def test_options_default(lib):
     lib.fif_options_default(ctypes.byref(o))
     assert (o.mask_rule, o.nu, o.max_inner, o.floor_tau) == (0, 1.6, 1_000_000, 1e-9)
     assert (o.stop_mode, o.gamma, o.peak_rho) == (0, 0.0, 0.1)
+    assert (o.window, o.window_points) == (None, 0)
 
 
 def _plan_status(lib, lengths, max_imfs=4, **opt):
@@ -79,6 +80,12 @@ def _plan_status(lib, lengths, max_imfs=4, **opt):
     ([4096], dict(mask_rule=2, peak_rho=1.5), -1),
     ([4096, 131072], dict(stop_mode=1), -1),   # stop modes 1, 2: lengths <= 65536
     ([262144], dict(stop_mode=2), -1),
+    ([4096], dict(window=[1.0]), -1),                 # fewer than two samples
+    ([4096], dict(window=[0.0, 1.0]), -1),            # first sample not > 0
+    ([4096], dict(window=[1.0, -0.5, 0.0]), -1),      # negative sample
+    ([4096], dict(window=[1.0, float("nan")]), -1),
+    ([4096], dict(window=np.ones(65538)), -1),        # too many samples
+    ([4096], dict(window=[1.0, 0.0], stop_mode=2), -1),
     ([], {}, -1),
 ])
 def test_plan_rejects_bad_arguments_on_host(lib, lengths, kw, status):
@@ -102,6 +109,10 @@ def test_single_rejects_bad_arguments_on_host(lib):
     assert lib.fif_decompose(p, 64, 0, 1e-3, 0, p, p, p, None, ctypes.byref(o), None) == -1
     bad = Options(max_inner=0).c()
     assert lib.fif_decompose(p, 64, 0, 1e-3, 4, p, p, p, None, ctypes.byref(bad), None) == -1
+    # the window argument and the options' samples must agree
+    assert lib.fif_decompose(p, 64, 1, 1e-3, 4, p, p, p, None, ctypes.byref(o), None) == -1
+    w = Options(window=[1.0, 0.5, 0.0]).c()
+    assert lib.fif_decompose(p, 64, 0, 1e-3, 4, p, p, p, None, ctypes.byref(w), None) == -1
 
 
 def test_batched_rejects_null_plan(lib):

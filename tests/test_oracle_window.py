@@ -53,6 +53,24 @@ def test_box_shape_is_a_squared_dirichlet_kernel(N, L):
     assert np.max(np.abs(lam[1:] - d * d)) <= 1e-14
 
 
+@pytest.mark.parametrize("N,L,K", [(128, 9, 5), (1000, 40, 17), (256, 200, 3), (97, 12, 64), (64, 50, 2)])
+def test_shape_eigenvalues_are_the_dft_of_the_column(N, L, K):
+    """(DFT h)^2 / (sum h)^2 = DFT of the folded h * h / (sum h)^2 (the
+    convolution theorem), up to rounding and the exact-zero reading."""
+    shape = np.random.default_rng(N + L).uniform(0.05, 1.0, K + 1)
+    a = fs.eigenvalues_shape(N, L, shape)
+    b = np.fft.fft(fs.window_column_shape(N, L, shape)).real
+    assert np.max(np.abs(a - b)) <= 1e-15
+
+
+def test_exact_zeros_of_a_box_spectrum():
+    """Shape [1, 1] at L = 2 is the box [1, 1, 1]: H_j = (1 + 2 cos(2 pi j/N))/3
+    vanishes at j = N/3 and 2N/3; those eigenvalues are exactly 0."""
+    lam = fs.eigenvalues_shape(30, 2, [1.0, 1.0])
+    assert lam[10] == 0.0 and lam[20] == 0.0
+    assert np.count_nonzero(lam == 0.0) == 2
+
+
 def test_shape_eigenvalues_lie_in_the_unit_interval():
     rng = np.random.default_rng(3)
     for N, L, K in ((128, 9, 5), (1000, 40, 17), (256, 200, 3), (97, 12, 64)):
