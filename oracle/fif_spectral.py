@@ -27,6 +27,16 @@ Variants beyond the plain method (each off by default):
     frequency peak" of the spectrum), read as L = ceil(N / f), f the highest
     bin 1 <= f <= N/2 whose power is >= peak_rho times the strongest
     non-constant bin's (a pure tone at f cycles then gets the L of rule 0);
+
+SD with the relative criterion (the default) is a weighted mean of lambda^2
+over the bins the residual holds, with weights P_j mu_j^(m-1).  Two readings
+keep it what exact arithmetic gives once m is large (the paper is silent):
+bins with |R_j|^2 < SD_NOISE max_{j>=1} |R_j|^2 are rounding noise of exact
+zeros (an FP64 FFT resolves R to ~1e-16 of its largest bin) and are left out
+of the sums; and the sums are taken scale-free, every weight divided by the
+largest, so that they never underflow.  Without either, a pure tone whose
+lambda exceeds delta (SD constant, the case the iteration cap exists for)
+would stop wherever the tone's power underflows or the noise takes over.
   - window=shape: another window than the triangle of equation 271.  Section
     4 only needs W's eigenvalues, the DFT of its first column (equation
     "Lambdas"), which can be tabulated for any filter.  Read here as: h, the
@@ -118,6 +128,10 @@ def eigenvalues_shape(N: int, L: int, shape) -> np.ndarray:
     return lam
 
 
+# |R_j|^2 below this fraction of the strongest non-constant bin is not counted in SD
+SD_NOISE = 1e-26
+
+
 def _pow1m(lam, e):
     """(1 - lambda)^e as exp(e log1p(-lambda)): the factor of equation
     "IMF1_direct" without rounding 1 - lambda first (whose relative error
@@ -204,15 +218,27 @@ def decompose(s, delta: float, max_imfs: int, *, mask_rule: int = 0, nu: float =
         mu = (1.0 - lam) ** 2
         lam2 = lam * lam
         flags = 0
+        if stop == "sd":
+            # the bins SD counts: the constant one and those above the noise floor
+            qmax = float(np.max(P[1:])) if N > 1 else 0.0
+            Psd = np.where(P >= SD_NOISE * qmax, P, 0.0)
+            Psd[0] = P[0]
         if stop == "sd" and search == "bisect":
             # SD_m is non-increasing in m, so the smallest m with SD_m <= delta
             # is found by doubling then bisection on the same Parseval sums
+            live = (Psd > 0.0) & (lam < 1.0)
+            with np.errstate(divide="ignore"):
+                l1 = np.log1p(-np.clip(lam, 0.0, 1.0))
+
             def sd_at(mm):
                 if mm == 1:
-                    num, den = float(np.sum(P * lam2)), float(np.sum(P))
+                    num, den = float(np.sum(Psd * lam2)), float(np.sum(Psd))
                 else:
-                    x = P * _pow1m(lam, 2 * (mm - 1))
-                    num, den = float(np.sum(x * lam2)), float(np.sum(x))
+                    if not np.any(live):
+                        return 0.0
+                    a = 2.0 * (mm - 1) * l1[live]
+                    x = Psd[live] * np.exp(a - a.max())
+                    num, den = float(np.sum(x * lam2[live])), float(np.sum(x))
                 return math.sqrt(num / den) if den > 0 else 0.0
             hi = 1
             while sd_at(hi) > delta and hi < max_inner:
@@ -232,8 +258,9 @@ def decompose(s, delta: float, max_imfs: int, *, mask_rule: int = 0, nu: float =
             sd = sd_at(m)
             sd_prev = sd_at(m - 1) if m > 1 else math.inf
         elif stop == "sd":
-            # N0 = 1, 2, ...: SD_{N0} = ||(1-lam)^{N0-1} lam R|| / ||(1-lam)^{N0-1} R||
-            x = P.copy()
+            # N0 = 1, 2, ...: SD_{N0} = ||(1-lam)^{N0-1} lam R|| / ||(1-lam)^{N0-1} R||,
+            # the weights rescaled by their largest after every step
+            x = Psd.copy()
             m = 0
             sd = 0.0
             sd_prev = math.inf
@@ -249,6 +276,9 @@ def decompose(s, delta: float, max_imfs: int, *, mask_rule: int = 0, nu: float =
                     flags |= dif.FLAG_CAP
                     break
                 x = x * mu
+                top = float(np.max(x))
+                if top > 0.0:
+                    x = x / top
         elif stop == "abs":
             # ||s_{m+1} - s_m||_2 = ||W s_m||_2 = sqrt(sum |R|^2 lam^2 mu^m / N) (Parseval)
             x = P * mu

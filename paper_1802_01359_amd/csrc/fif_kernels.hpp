@@ -353,6 +353,10 @@ __device__ __forceinline__ double ipow(double x, int64_t e)
     return r;
 }
 
+// Noise floor of the relative stop test: bins with |R_j|^2 below this
+// fraction of the strongest non-constant bin's are not counted in SD.
+constexpr double kSdNoise = 1e-26;
+
 // Exponent above which (1 - lambda)^e is taken as exp(e log1p(-lambda)):
 // binary powering carries a relative error of about e ulps of 1 - lambda.
 constexpr int64_t kPowByMul = 1023;
@@ -818,8 +822,10 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
             // spec_pos); all of a thread's loads are issued first
             constexpr int PQ = kTileCap / 2 / kFftThreads + 1;
             double2 vv[PQ];
-            // deferred FP64 check of m: this tile's part of the stop-test sums
+            // deferred FP64 check of m: this tile's part of the stop-test sums,
+            // over the bins above the scan's noise floor
             const bool chk = MODE == MODE_STEP && S->chk;
+            const double qthr = chk ? S->qthr : 0.0;
             double cs[4] = {0.0, 0.0, 0.0, 0.0};
             const int64_t pbase = (int64_t)w.tile * owners;
 #pragma unroll
@@ -862,7 +868,7 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
                         y = (m >= 2) ? z * om : 1.0;
                         g = y * om;
                     }
-                    if (chk) {
+                    if (chk && v.x * v.x + v.y * v.y >= qthr) {
                         const double P = ((2 * k == N) ? 1.0 : 2.0) * (v.x * v.x + v.y * v.y);
                         const double l2 = lam * lam;
                         cs[0] += P * l2 * y * y;
@@ -1313,7 +1319,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
     const double inv_np = 1.0 / ((double)N * pscale);
     const float lnthr_abs = (float)log(delta * delta * (double)N * pscale);
     auto ok = [&](double sd) { return SMODE != 0 ? sd < delta : sd <= delta; };
-    double mz = 0.0;          // largest |R_j|^2 (stop mode 2)
+    double mz = 0.0;          // largest |R_j|^2, j >= 1 (stop modes 0 and 2)
 
     // ---- first sweep: FP32 copies of the weighted power b, power*lambda^2
     //      a, and tau = log2 mu, mu = (1 - lambda)^2 (DC kept aside since
@@ -1348,7 +1354,6 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
             if (j <= nh) {
                 v[g] = R[pos_small(smap, j)];
                 jb[g] = j;
-                if (SMODE == 2) mz = fmax(mz, v[g].x * v[g].x + v[g].y * v[g].y);
             }
         }
 #pragma unroll
@@ -1358,7 +1363,11 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
             float av = 0.f;
             tau_r[i] = 0.f;
             b_r[i] = 0.f;
-            if (j <= nh) sweep_bin(v[g], jb[g], tau_r[i], av, b_r[i]);
+            if (j <= nh) {
+                sweep_bin(v[g], jb[g], tau_r[i], av, b_r[i]);
+                // after the group's loads were issued, not between them
+                if (SMODE != 1) mz = fmax(mz, v[g].x * v[g].x + v[g].y * v[g].y);
+            }
             lds_a[i * T + tid] = av;
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -1549,10 +1558,14 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
     //      accepts the estimate or sends the signal back here (redo_only)
     if (SMODE == 0 && A.defer && !A.redo_only && lp.two_pass && lp.paired) {
         if (A.mt_shift) mt = max((int64_t)1, min(cap, mt + (int64_t)A.mt_shift));
+        // the check in pass 1 counts the same bins as the FP64 evaluation here
+        double mn_unused = INFINITY, qm = mz;
+        block_minmax<T>(mn_unused, qm, shd);
         if (tid == 0) {
             S->L = L;
             S->m = mt;
             S->chk = 1;
+            S->qthr = kSdNoise * qm;
             if (A.info) {
                 fif_imf_info* I = A.info + (int64_t)s * A.max_imfs + A.t;
                 I->k = S->k;
@@ -1565,9 +1578,25 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
         return;
     }
 
-    // ---- FP64 SD at m and m-1 (Parseval, FP64 lambda, powers and sums)
+    // ---- FP64 SD at m and m-1 (Parseval, FP64 lambda, powers and sums).
+    //      Stop mode 0: SD_m^2 is a P mu^(m-1)-weighted mean of lambda^2, so
+    //      for large m it is decided by the bins that decay slowest.  Bins
+    //      below the noise floor (|R_j|^2 < kSdNoise max_{j>=1} |R_j|^2:
+    //      rounding-level content, of the input or of exact zeros) are left
+    //      out (the deferred check in pass 1 does the same), and the weights are
+    //      summed relative to the largest one (a running maximum of the
+    //      exponent, as in a streaming log-sum-exp), so that the sums never
+    //      underflow and SD tends to the smallest counted lambda, as in exact
+    //      arithmetic.  The FP32 search above only brackets m; this decides.
+    double qthr = -1.0;
     auto sd64 = [&](int64_t m, double& sd_m, double& sd_mm1) {
+        if (SMODE == 0 && qthr < 0.0) {
+            double mn_unused = INFINITY, qm = mz;
+            block_minmax<T>(mn_unused, qm, shd);
+            qthr = kSdNoise * qm;
+        }
         double v[4] = {0.0, 0.0, 0.0, 0.0};
+        double amax = -INFINITY;  // stop mode 0, e >= 1: sums are relative to exp(amax)
         const int64_t e = m - 2;  // exponent of mu at m-1; may be -1
         constexpr int DG = 4;     // bins whose loads are issued together
         for (int j0 = 1 + tid; j0 <= nh; j0 += DG * T) {
@@ -1588,25 +1617,60 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
             if (j0 + g * T > nh) break;
             const double2 z = zz[g];
             const int64_t jb = jj[g];
-            const double P = weight(jb) * (z.x * z.x + z.y * z.y) * pscale;
+            const double q = z.x * z.x + z.y * z.y;
+            if (SMODE == 0 && q < qthr) continue;   // below the noise floor
+            const double P = weight(jb) * q * pscale;
             const double lam = lambda_at(jb, lw);
             const double l2 = lam * lam;
             const double om = 1.0 - lam;
-            double xe;  // mu^e
-            if (e < 0)
-                xe = 0.0;
-            else if (lam >= 1.0)
-                xe = (e == 0) ? 1.0 : 0.0;
-            else if (e <= kPowByMul)
-                xe = ipow(om * om, e);
-            else
-                xe = exp((double)e * 2.0 * log1p(-lam));
-            const double xm = (e < 0) ? 1.0 : xe * om * om;  // mu^(m-1)
+            double xe, xm;  // mu^e, mu^(m-1) (stop mode 0, e >= 1: times exp(-amax))
+            if (SMODE == 0) {
+                if (e < 0) {
+                    xe = 0.0;
+                    xm = 1.0;
+                } else if (lam >= 1.0) {
+                    xe = (e == 0) ? 1.0 : 0.0;
+                    xm = 0.0;
+                } else if (e == 0) {
+                    xe = 1.0;
+                    xm = om * om;
+                } else {
+                    const double a = (double)e * 2.0 * log1p(-lam);
+                    if (a > amax) {
+                        const double r = (amax == -INFINITY) ? 0.0 : exp(amax - a);
+                        v[0] *= r;
+                        v[1] *= r;
+                        v[2] *= r;
+                        v[3] *= r;
+                        amax = a;
+                    }
+                    xe = exp(a - amax);
+                    xm = xe * om * om;
+                }
+            } else {
+                if (e < 0)
+                    xe = 0.0;
+                else if (lam >= 1.0)
+                    xe = (e == 0) ? 1.0 : 0.0;
+                else if (e <= kPowByMul)
+                    xe = ipow(om * om, e);
+                else
+                    xe = exp((double)e * 2.0 * log1p(-lam));
+                xm = (e < 0) ? 1.0 : xe * om * om;
+            }
             v[0] += P * l2 * xe;
             v[1] += P * xe;
             v[2] += P * l2 * xm;
             v[3] += P * xm;
           }
+        }
+        if (SMODE == 0 && e >= 1) {
+            // bring every thread's sums to the block's largest exponent
+            double mn_unused = INFINITY, am = amax;
+            block_minmax<T>(mn_unused, am, shd);
+            const double r = (amax == -INFINITY) ? 0.0 : exp(amax - am);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[k] *= r;
         }
         if (tid == 0) {
             if (m == 1) {

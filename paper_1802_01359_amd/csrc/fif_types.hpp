@@ -94,6 +94,7 @@ struct SigState {
     int64_t fpeak;                 // spectral-peak bin of this step (mask rule 2)
     double sd, sd_prev;
     double mean, maxabs, pscale;
+    double qthr;                   // noise floor of the relative stop test (deferred check)
     // min / max of the residual of the current outer step as order-preserving
     // integer keys, accumulated with atomics (order independent)
     long long kmin, kmax;

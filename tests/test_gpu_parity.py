@@ -17,6 +17,7 @@ import pytest
 
 import siggen
 from oracle import dif
+from oracle import fif_spectral as fs
 
 pytestmark = pytest.mark.gpu
 
@@ -221,6 +222,29 @@ def test_cap_on_a_pure_tone():
     assert int(res.info["m"][0]) == 50 == ref.m[0]
     assert res.info["flags"][0] & fif.IMF_CAP
     assert abs(res.info["sd"][0] - ref.sd[0]) < 1e-13
+
+
+@pytest.mark.parametrize("N,k0", [(256, 8), (65536, 700)])
+def test_pure_tone_runs_to_the_default_cap(N, k0):
+    """A pure tone whose lambda exceeds delta has SD_m = lambda for every m:
+    the answer is the cap (10^6, far past the step where the tone's weight
+    underflows FP64), with SD = lambda, on both sides.  N = 65536 takes the
+    deferred check in pass 1, which fails there and sends the step to the
+    exact search."""
+    s = np.cos(2 * np.pi * k0 * np.arange(N) / N + 0.3)
+    delta = 5e-4
+    ref = fs.decompose(s, delta, 1, mask_rule=1, search="bisect")
+    assert ref.m[0] == 1_000_000 and ref.flags[0] & 1
+    x = torch.tensor(s, dtype=torch.float64, device="cuda")
+    print("pure tone N=%d k0=%d" % (N, k0), flush=True)
+    res = fif.decompose(x, delta, 1, fif.Options(mask_rule=1))
+    torch.cuda.synchronize()
+    assert int(res.info["L"][0]) == ref.L[0]
+    assert int(res.info["m"][0]) == 1_000_000
+    assert res.info["flags"][0] & fif.IMF_CAP
+    assert res.info["sd"][0] == pytest.approx(ref.sd[0], rel=1e-9)
+    imf = res.imfs[0].cpu().numpy()
+    assert np.linalg.norm(imf - ref.imfs[0]) <= 1e-12 * np.linalg.norm(s)
 
 
 @pytest.mark.parametrize("N", [4096, 65536])

@@ -57,12 +57,12 @@ def test_window_shape_fp32_large(shape):
 def test_window_shape_with_other_variants():
     _batch_vs_oracle(SMALL, 1e-2, 4, torch.float64, dict(window=RAISED_COS, stop="abs", gamma=1e-2), LAM_ABS,
                      window=RAISED_COS, stop_mode=1, gamma=1e-2)
-    # without the 30-sample noise signal: there the peak rule gives L = 2, the
-    # flat top is then a 3-tap box whose spectrum has exact zeros, and after
-    # the first IMF every bin left has lambda > delta, so SD_m cannot reach
-    # delta and the search ends where FP64 underflows (implementation-
-    # dependent m; a degenerate input, not a parity case)
-    _batch_vs_oracle([4096, 1000, 8192, 12000, 65536], 1e-3, 4, torch.float64, dict(window=FLAT_TOP, mask_rule=2),
+    # on the 30-sample noise signal the peak rule gives L = 2: the flat top is
+    # then a 3-tap box whose spectrum has exact zeros, and after the first IMF
+    # every bin left has lambda > delta, so SD_m cannot reach delta: the later
+    # IMFs run to the cap on both sides (the oracle bisects, which its pins
+    # tie to the linear scan)
+    _batch_vs_oracle(SMALL, 1e-3, 4, torch.float64, dict(window=FLAT_TOP, mask_rule=2, search="bisect"),
                      LAM_ABS, window=FLAT_TOP, mask_rule=2)
 
 

@@ -175,3 +175,57 @@ def test_peak_rule_picks_the_highest_significant_peak():
         assert fs.peak_frequency(R, rho) == f_exp
         d = fs.decompose(s, 1e-3, 1, mask_rule=2, peak_rho=rho)
         assert d.L[0] == -(-N // f_exp)
+
+
+# ------------------------------------------- degenerate SD tails (cap) --
+
+def _lam_tone(N, L, k0):
+    return float(np.sin(np.pi * L * k0 / N) / (L * np.sin(np.pi * k0 / N))) ** 4
+
+
+@pytest.mark.parametrize("search", ["linear", "bisect"])
+def test_pure_tone_above_delta_runs_to_the_cap(search):
+    """A pure DFT mode has SD_m = lambda_k0 for every m (an eigenvector of W),
+    so with lambda_k0 > delta no m satisfies the test: m is the cap, SD stays
+    lambda_k0.  The paper's mask rule puts lambda_k0 near 1.6e-3; the cap is
+    past the step where the tone's weight mu^(m-1) underflows FP64."""
+    N, k0, delta = 256, 8, 5e-4
+    cap = 1_000_000 if search == "bisect" else 300_000
+    s = _tone(N, k0)
+    d = fs.decompose(s, delta, 1, mask_rule=1, max_inner=cap, search=search)
+    lam = _lam_tone(N, d.L[0], k0)
+    assert lam > delta
+    assert 2 * (cap - 1) * math.log1p(-lam) < math.log(1e-308)
+    assert d.m[0] == cap and d.flags[0] & 1
+    assert d.sd[0] == pytest.approx(lam, rel=1e-12)
+
+
+def test_pure_tone_below_delta_stops_at_once():
+    N, k0 = 1024, 3
+    s = _tone(N, k0)
+    d = fs.decompose(s, 0.5, 1)
+    assert _lam_tone(N, d.L[0], k0) <= 0.5 and d.m[0] == 1
+
+
+def test_two_tones_cross_over_where_the_closed_form_says():
+    """Tone k0 with lambda0 > delta plus a tone k1 of power ratio eps with
+    lambda1 < delta: SD_m^2 = (lambda0^2 q + lambda1^2) / (q + 1), q =
+    (P0/P1) (mu0/mu1)^(m-1), reaches delta^2 at a closed-form m; the weaker
+    tone is counted (far above the noise floor)."""
+    N, delta = 4096, 1e-3
+    k0, k1, amp1 = 5, 23, 1e-9
+    s = _tone(N, k0) + amp1 * _tone(N, k1, phase=1.1)
+    d = fs.decompose(s, delta, 1, mask_rule=1, search="bisect")
+    L = d.L[0]
+    l0, l1 = _lam_tone(N, L, k0), _lam_tone(N, L, k1)
+    assert l0 > delta > l1
+    lp = 2.0 * math.log(1.0 / amp1)                       # log(P0 / P1)
+    lr = 2.0 * (math.log1p(-l0) - math.log1p(-l1))        # log(mu0 / mu1) < 0
+    m = 1
+    while True:
+        q = math.exp(lp + (m - 1) * lr)
+        if (l0 * l0 * q + l1 * l1) / (q + 1.0) <= delta * delta:
+            break
+        m += 1
+    assert m > 1000 and d.m[0] == m
+    assert fs.decompose(s, delta, 1, mask_rule=1).m[0] == m     # linear scan alike
