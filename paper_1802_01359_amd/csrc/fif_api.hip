@@ -135,7 +135,7 @@ struct fif_plan {
     int32_t* d_itab = nullptr;
     // workspace layout (byte offsets)
     size_t ws_state = 0, ws_spec0 = 0, ws_spec1 = 0, ws_inter = 0, ws_parts = 0, ws_psum = 0, ws_gscr = 0,
-           ws_bigs = 0, ws_bpart = 0, ws_resid = 0, ws_feat = 0, ws_prop = 0, ws_chk = 0, ws_total = 0;
+           ws_bigs = 0, ws_bpart = 0, ws_bqmax = 0, ws_resid = 0, ws_feat = 0, ws_prop = 0, ws_chk = 0, ws_total = 0;
     // sampled window shape: its samples (in the FP64 table at wshape_off),
     // and the workspace of the per-step eigenvalue tables
     std::vector<double> wshape;
@@ -550,6 +550,8 @@ fif_status fif_plan_create(fif_plan** out, const int64_t* lengths, int32_t B, in
     ws += sizeof(BigScan) * (size_t)nbig;
     p->ws_bpart = ws = align_up(ws, 256);
     ws += sizeof(double) * 2 * kBigCand * (size_t)btiles;
+    p->ws_bqmax = ws = align_up(ws, 256);
+    ws += sizeof(double) * (size_t)btiles;
     p->ws_resid = ws = align_up(ws, 256);
     ws += sizeof(double) * (size_t)resid;
     p->ws_feat = ws = align_up(ws, 256);
@@ -748,6 +750,7 @@ Bound bind(const fif_plan* p, void* ws, double delta, fif_imf_info* info)
     S.gscr = (float*)(w + p->ws_gscr);
     S.bigs = (BigScan*)(w + p->ws_bigs);
     S.bpart = (double*)(w + p->ws_bpart);
+    S.bqmax = (double*)(w + p->ws_bqmax);
     S.info = info;
     S.prop = nullptr;
     S.t = 0;

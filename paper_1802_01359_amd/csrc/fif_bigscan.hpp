@@ -78,6 +78,7 @@ __global__ __launch_bounds__(T) void k_bscan_prep(ScanArgs A)
             G->phase = 0;
             G->L = L;
             G->pscale = sh_d[0];
+            G->qthr = 0.0;
             G->n32 = G->n64 = 0;
             G->flags = 0;
             G->lo = 0;
@@ -211,10 +212,29 @@ __device__ __forceinline__ void bscan_tile_sums(const ScanArgs& A, const SigDesc
         // position -> bin table of this length, read once (null: bin order)
         const int32_t* btab = lp.spec_perm ? A.itab + lp.bin_off : nullptr;
         const double pscale = G->pscale;
+        // relative stop test, as in k_scan: bins below the noise floor are
+        // not counted, and each candidate's sums are kept relative to the
+        // largest weight (running maximum of the exponent per thread, then the
+        // block's); the tile hands over the logarithms of its two sums
+        const double qthr = G->qthr;
         for (int c = 0; c < nc; c += 2) {
             const int64_t e0 = G->cand[c] - 1;
             const int64_t e1 = (c + 1 < nc) ? G->cand[c + 1] - 1 : -1;
             double acc[4] = {0.0, 0.0, 0.0, 0.0};
+            double am[2] = {-INFINITY, -INFINITY};
+            auto add = [&](int k, int64_t e, double P, double l2, double lam, double lg) {
+                if (e < 0 || (e > 0 && lam >= 1.0)) return;
+                const double a = (e == 0) ? 0.0 : (double)e * lg;
+                if (a > am[k]) {
+                    const double r = (am[k] == -INFINITY) ? 0.0 : exp(am[k] - a);
+                    acc[2 * k] *= r;
+                    acc[2 * k + 1] *= r;
+                    am[k] = a;
+                }
+                const double x = exp(a - am[k]);
+                acc[2 * k] += P * l2 * x;
+                acc[2 * k + 1] += P * x;
+            };
             constexpr int DG = 4;  // bins whose loads are issued together
             for (int q0 = 0; q0 < BPT; q0 += DG) {
               double2 zz[DG];
@@ -234,45 +254,54 @@ __device__ __forceinline__ void bscan_tile_sums(const ScanArgs& A, const SigDesc
                 if (j0 + tid + (q0 + g) * T > nh) break;
                 const double2 z = zz[g];
                 const int64_t jb = jj[g];
-                const double P = ((2 * jb == d.N) ? 1.0 : 2.0) * (z.x * z.x + z.y * z.y) * pscale;
+                const double q = z.x * z.x + z.y * z.y;
+                if (q < qthr) continue;
+                const double P = ((2 * jb == d.N) ? 1.0 : 2.0) * q * pscale;
                 const double lam = lambda_at(jb, lw);
                 const double l2 = lam * lam;
-                const double mu = (1.0 - lam) * (1.0 - lam);
-                double x0, x1 = 0.0;
-                if (lam >= 1.0) {
-                    x0 = (e0 == 0) ? 1.0 : 0.0;
-                    x1 = (e1 == 0) ? 1.0 : 0.0;
-                } else {
-                    x0 = (e0 <= kPowByMul) ? ipow(mu, e0) : exp((double)e0 * 2.0 * log1p(-lam));
-                    if (e1 == e0 + 1)
-                        x1 = x0 * mu;
-                    else if (e1 >= 0)
-                        x1 = (e1 <= kPowByMul) ? ipow(mu, e1) : exp((double)e1 * 2.0 * log1p(-lam));
-                }
-                acc[0] += P * l2 * x0;
-                acc[1] += P * x0;
-                acc[2] += P * l2 * x1;
-                acc[3] += P * x1;
+                const double lg = (lam < 1.0) ? 2.0 * log1p(-lam) : 0.0;
+                add(0, e0, P, l2, lam, lg);
+                add(1, e1, P, l2, lam, lg);
               }
+            }
+            double mk[2];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                double mn_unused = INFINITY, M = am[k];
+                block_minmax<T>(mn_unused, M, shd);
+                const double r = (am[k] == -INFINITY) ? 0.0 : exp(am[k] - M);
+                acc[2 * k] *= r;
+                acc[2 * k + 1] *= r;
+                mk[k] = M;
             }
             block_sum<double, T, 4>(acc, shd);
             if (tid == 0) {
-                out[2 * c] = acc[0];
-                out[2 * c + 1] = acc[1];
+                // log(0) = -inf: an empty sum
+                out[2 * c] = log(acc[0]) + mk[0];
+                out[2 * c + 1] = log(acc[1]) + mk[0];
                 if (c + 1 < nc) {
-                    out[2 * c + 2] = acc[2];
-                    out[2 * c + 3] = acc[3];
+                    out[2 * c + 2] = log(acc[2]) + mk[1];
+                    out[2 * c + 3] = log(acc[3]) + mk[1];
                 }
             }
         }
     }
-    // DC bin (lambda_0 = 1): contributes to m = 1 only
+    // DC bin (lambda_0 = 1): contributes to m = 1 only (FP64 phase: to the
+    // logarithms of the sums)
     if (tile == 0 && tid == 0) {
         const double P0 = (R[0].x * R[0].x + R[0].y * R[0].y) * G->pscale;
         for (int i = 0; i < nc; ++i)
             if (G->cand[i] == 1) {
-                out[2 * i] += P0;
-                out[2 * i + 1] += P0;
+                if (ph < 2) {
+                    out[2 * i] += P0;
+                    out[2 * i + 1] += P0;
+                } else if (P0 > 0.0) {
+                    for (int k = 0; k < 2; ++k) {
+                        const double u = out[2 * i + k], v = log(P0);
+                        const double hi = fmax(u, v), lo = fmin(u, v);
+                        out[2 * i + k] = hi + log1p(exp(lo - hi));
+                    }
+                }
             }
     }
     __syncthreads();
@@ -282,27 +311,46 @@ __device__ __forceinline__ void bscan_tile_sums(const ScanArgs& A, const SigDesc
 // (numerator) and tot[2i+1] (denominator) of candidate i.  kDecideGroups
 // groups of 64 threads each add a contiguous range of tiles in tile order;
 // the group results are then added in group order, so the result depends
-// only on the number of tiles.
+// only on the number of tiles.  LOGS (FP64 phase): the partial sums are
+// logarithms, added as a log-sum-exp (each group relative to its largest,
+// then the groups relative to theirs); tot holds logarithms too.
 constexpr int kDecideGroups = 16;
 static_assert(2 * kBigCand <= 64, "one lane per partial sum");
-__device__ __forceinline__ void bscan_tile_totals(const ScanArgs& A, const SigDesc& d, int nc, double* part,
-                                                  double* tot)
+__device__ __forceinline__ void bscan_tile_totals(const ScanArgs& A, const SigDesc& d, int nc, bool logs,
+                                                  double* part, double* partm, double* tot)
 {
     const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
     const int nt = d.n_btiles;
     const int t0 = (int)(((int64_t)nt * g) / kDecideGroups), t1 = (int)(((int64_t)nt * (g + 1)) / kDecideGroups);
-    double s = 0.0;
+    double s = 0.0, mx = -INFINITY;
     if (c < 2 * nc) {
         const double* P = A.bpart + (int64_t)d.bt_off * 2 * kBigCand + c;
+        if (!logs) {
 #pragma unroll 8
-        for (int t = t0; t < t1; ++t) s += P[(int64_t)t * 2 * kBigCand];
+            for (int t = t0; t < t1; ++t) s += P[(int64_t)t * 2 * kBigCand];
+        } else {
+            for (int t = t0; t < t1; ++t) mx = fmax(mx, P[(int64_t)t * 2 * kBigCand]);
+            if (mx > -INFINITY)
+                for (int t = t0; t < t1; ++t) s += exp(P[(int64_t)t * 2 * kBigCand] - mx);
+        }
     }
     part[threadIdx.x] = s;
+    partm[threadIdx.x] = mx;
     __syncthreads();
     if (g == 0) {
-        double v = 0.0;
-        for (int q = 0; q < kDecideGroups; ++q) v += part[q * 64 + c];
-        tot[c] = v;
+        if (!logs) {
+            double v = 0.0;
+            for (int q = 0; q < kDecideGroups; ++q) v += part[q * 64 + c];
+            tot[c] = v;
+        } else {
+            double M = -INFINITY;
+            for (int q = 0; q < kDecideGroups; ++q) M = fmax(M, partm[q * 64 + c]);
+            double v = 0.0;
+            if (M > -INFINITY)
+                for (int q = 0; q < kDecideGroups; ++q)
+                    if (partm[q * 64 + c] > -INFINITY) v += part[q * 64 + c] * exp(partm[q * 64 + c] - M);
+            tot[c] = (M > -INFINITY) ? M + log(v) : -INFINITY;
+        }
     }
 }
 
@@ -361,12 +409,12 @@ __device__ __forceinline__ void bscan_decide(const ScanArgs& A, const SigDesc& d
         }
         return;
     }
-    // FP64 phase
+    // FP64 phase: tot holds the logarithms of the sums (-inf: empty)
     G->n64 += 1;
     int64_t elo = G->elo, ehi = G->ehi;
     double sd_lo = G->sd_lo, sd_hi = G->sd_hi;
     for (int i = 0; i < nc; ++i) {
-        const double sd = Bsum[2 * i] > 0.0 ? sqrt(Asum[2 * i] / Bsum[2 * i]) : 0.0;
+        const double sd = Bsum[2 * i] > -INFINITY ? exp(0.5 * (Asum[2 * i] - Bsum[2 * i])) : 0.0;
         const int64_t c = G->cand[i];
         if (sd <= delta) {
             if (ehi < 0 || c < ehi) {
@@ -425,6 +473,7 @@ __global__ __launch_bounds__(T) void k_bscan_round(ScanArgs A, const Work* __res
         // position -> bin table of this length, read once (null: bin order)
         const int32_t* btab = lp.spec_perm ? A.itab + lp.bin_off : nullptr;
         const double pscale = G->pscale;
+        double qmx = 0.0;      // largest |R_j|^2 of the tile (noise floor of the FP64 phase)
         constexpr int SG = 4;  // bins whose loads are issued together
         for (int q0 = 0; q0 < BPT; q0 += SG) {
           double2 zz[SG];
@@ -445,6 +494,7 @@ __global__ __launch_bounds__(T) void k_bscan_round(ScanArgs A, const Work* __res
             if (j > nh) break;
             const double2 z = zz[g];                   // storage position j
             const int64_t jb = jj[g];                  // its bin
+            qmx = fmax(qmx, z.x * z.x + z.y * z.y);
             const double P = ((2 * jb == d.N) ? 1.0 : 2.0) * (z.x * z.x + z.y * z.y) * pscale;
             const double lam = lambda_at(jb, lw);
             bv[j - 1] = (float)P;
@@ -452,7 +502,10 @@ __global__ __launch_bounds__(T) void k_bscan_round(ScanArgs A, const Work* __res
             tau[j - 1] = 2.8853900817779268f * log1pf(-(float)lam);
           }
         }
-        // each thread reads back only its own bins below: no barrier needed
+        double mn_unused = INFINITY;
+        block_minmax<T>(mn_unused, qmx, shd);
+        if (threadIdx.x == 0) A.bqmax[d.bt_off + w.tile] = qmx;
+        // each thread reads back only its own bins below
     }
     bscan_tile_sums<T, BPT>(A, d, lp, G, w.tile, shv, shf, shd);
     double* P = A.bpart + ((int64_t)d.bt_off + w.tile) * 2 * kBigCand;
@@ -464,14 +517,23 @@ __global__ __launch_bounds__(T) void k_bscan_round(ScanArgs A, const Work* __res
 __global__ __launch_bounds__(64 * kDecideGroups) void k_bscan_decide(ScanArgs A)
 {
     __shared__ double part[64 * kDecideGroups];
+    __shared__ double partm[64 * kDecideGroups];
     __shared__ double tot[2 * kBigCand];
     const int s = A.list[blockIdx.x];
     const SigDesc d = A.sigs[s];
     BigScan* G = A.bigs + d.bs;
     if (G->phase >= 3) return;
-    bscan_tile_totals(A, d, G->ncand, part, tot);
+    bscan_tile_totals(A, d, G->ncand, G->phase >= 2, part, partm, tot);
     __syncthreads();
-    if (threadIdx.x == 0) bscan_decide(A, d, G, tot);
+    if (threadIdx.x == 0) {
+        if (G->phase < 2 && G->n32 == 0) {
+            // after the sweep: the noise floor from the tiles' largest |R_j|^2
+            double q = 0.0;
+            for (int t = 0; t < d.n_btiles; ++t) q = fmax(q, A.bqmax[d.bt_off + t]);
+            G->qthr = kSdNoise * q;
+        }
+        bscan_decide(A, d, G, tot);
+    }
 }
 
 template <int T>

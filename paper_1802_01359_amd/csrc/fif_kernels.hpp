@@ -1127,6 +1127,7 @@ struct ScanArgs {
     float* gscr;              // FP32 scratch of the multi-workgroup scan (SigDesc::gs_off)
     BigScan* bigs;            // multi-workgroup scan states (SigDesc::bs)
     double* bpart;            // per-tile partial sums, 2*kBigCand per tile (SigDesc::bt_off)
+    double* bqmax;            // per-tile largest |R_j|^2 of the multi-workgroup scan
     fif_imf_info* info;       // [B][max_imfs] or null
     const int64_t* prop;      // proposed m per signal (0: none), or null
     int t;

@@ -74,6 +74,7 @@ struct BigScan {
     int64_t mt;                    // FP32 estimate
     int64_t m, L;
     double sd_lo, sd_hi, sd_m, sd_p, pscale;
+    double qthr;                   // noise floor of the FP64 phase (relative stop test)
     int64_t cand[kBigCand];
     int32_t phase;                 // 0 first round, 1 FP32 refine, 2 FP64, 3 done, 4 inactive
     int32_t ncand;

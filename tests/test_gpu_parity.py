@@ -224,13 +224,13 @@ def test_cap_on_a_pure_tone():
     assert abs(res.info["sd"][0] - ref.sd[0]) < 1e-13
 
 
-@pytest.mark.parametrize("N,k0", [(256, 8), (65536, 700)])
+@pytest.mark.parametrize("N,k0", [(256, 8), (65536, 700), (131072, 1400)])
 def test_pure_tone_runs_to_the_default_cap(N, k0):
     """A pure tone whose lambda exceeds delta has SD_m = lambda for every m:
     the answer is the cap (10^6, far past the step where the tone's weight
     underflows FP64), with SD = lambda, on both sides.  N = 65536 takes the
     deferred check in pass 1, which fails there and sends the step to the
-    exact search."""
+    exact search; N = 131072 the multi-workgroup search."""
     s = np.cos(2 * np.pi * k0 * np.arange(N) / N + 0.3)
     delta = 5e-4
     ref = fs.decompose(s, delta, 1, mask_rule=1, search="bisect")
