@@ -24,6 +24,11 @@ Workloads (synthetic, seeded; see siggen):
   window  the chirps batch with a sampled window shape (raised cosine,
           33 samples) instead of the triangle: every outer step tabulates
           the eigenvalues from a forward transform of the folded taps
+
+--variant applies one of the paper's variants of the method to the chosen
+workload: gamma (thresholded IMF, gamma = 0.01), abs (absolute stop
+criterion), apriori (the a-priori N0 of Theorem 5, no search), rule1 (mask
+length 2 floor(1.6 N/k)), peak (spectral-peak mask length, rho = 0.1).
 """
 from __future__ import annotations
 
@@ -50,6 +55,15 @@ def log(*a):
 
 
 RAISED_COS_33 = [0.5 * (1.0 + float(np.cos(np.pi * i / 32))) for i in range(33)]
+
+# option sets of the library (fif_options) and of the spectral oracle per variant
+VARIANTS = {
+    "gamma": (dict(gamma=1e-2), dict(gamma=1e-2)),
+    "abs": (dict(stop_mode=1), dict(stop="abs")),
+    "apriori": (dict(stop_mode=2), dict(stop="apriori")),
+    "rule1": (dict(mask_rule=1), dict(mask_rule=1)),
+    "peak": (dict(mask_rule=2, peak_rho=0.1), dict(mask_rule=2, peak_rho=0.1)),
+}
 
 
 def workload(name: str):
@@ -134,19 +148,19 @@ def algorithmic_bytes(kind: str, lengths, n_imfs, max_imfs: int, esize: int) -> 
     return 0.0                                              # bookkeeping / implementation-only kernels
 
 
-def cpu_baseline(sigs, delta, max_imfs, want: int, budget_s: float, threads: int, window=None):
+def cpu_baseline(sigs, delta, max_imfs, want: int, budget_s: float, threads: int, window=None, okw=None):
     """The oracle, one signal per host thread (the C oracle releases the GIL),
     over rounds of `threads` signals until `want` signals or the budget.  A
-    sampled window shape runs the FP64 spectral oracle (numpy) instead, the
-    time-domain one having only the triangle."""
+    sampled window shape or a variant runs the FP64 spectral oracle (numpy)
+    instead, the time-domain one having only the plain method."""
     from concurrent.futures import ThreadPoolExecutor
     from oracle import dif
     from oracle import fif_spectral
 
     def one(s):
         s = np.asarray(s, dtype=np.float64)
-        if window is not None:
-            return fif_spectral.decompose(s, delta, max_imfs, window=window)
+        if window is not None or okw:
+            return fif_spectral.decompose(s, delta, max_imfs, window=window, **(okw or {}))
         return dif.decompose(s, delta, max_imfs)
     t0 = time.perf_counter()
     done = 0
@@ -167,6 +181,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="chirps", choices=["chirps", "uneven", "long", "tones3", "plain", "learned", "window"])
+    ap.add_argument("--variant", default=None, choices=sorted(VARIANTS), help="a variant of the method (see above)")
     ap.add_argument("--model", default=MODEL_FILE, help="proposal network file (learned workload)")
     ap.add_argument("--cpu-signals", type=int, default=8, help="signals the CPU oracle decomposes at most")
     ap.add_argument("--cpu-threads", type=int, default=1,
@@ -187,6 +202,11 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     W = workload(args.workload)
+    lib_opt, oracle_opt = VARIANTS[args.variant] if args.variant else ({}, {})
+    if args.variant:
+        if args.workload in ("plain", "learned", "window"):
+            raise SystemExit("--variant applies to the batched workloads chirps, uneven, long, tones3")
+        W["workload"] += "+" + args.variant
     lengths = W["lengths"]
     log("generating %s ..." % W["workload"])
     t0 = time.perf_counter()
@@ -226,7 +246,7 @@ def main():
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
     else:
-        plan = fif.Plan(lengths, J, fif.Options(window=W.get("window")))
+        plan = fif.Plan(lengths, J, fif.Options(window=W.get("window"), **lib_opt))
         out = plan.alloc_outputs(dt)
         model = None
         if args.workload == "learned":
@@ -329,6 +349,8 @@ def main():
                    ("batched, learned proposal of m" if args.workload == "learned" else
                     ("batched, sampled window shape" if args.workload == "window" else "batched"))},
     }
+    if args.variant:
+        res["config"]["variant"] = {"name": args.variant, "options": lib_opt}
     if args.workload not in ("plain",) and extra:
         res["config"].update(extra)
     if roofline is not None:
@@ -336,12 +358,13 @@ def main():
     if not args.no_cpu_baseline:
         threads = max(1, args.cpu_threads)
         done, samples, cel = cpu_baseline(sigs, delta, J, args.cpu_signals, args.cpu_budget, threads,
-                                          W.get("window"))
+                                          W.get("window"), oracle_opt)
         res["cpu_baseline"] = {
             "value": samples / cel, "unit": "samples/s", "cores": threads, "kind": "oracle",
             "sample": "first %d of %d signals of the same workload, full decomposition by the FP64 "
                       "%s oracle, one signal per thread, %d threads, %.1f s" % (
-                          done, len(lengths), "spectral (numpy)" if W.get("window") else "time-domain (C)",
+                          done, len(lengths),
+                          "spectral (numpy)" if (W.get("window") or oracle_opt) else "time-domain (C)",
                           threads, cel)}
     print(json.dumps(res), flush=True)
 
