@@ -141,15 +141,25 @@ template <bool INV> struct Dft<3, INV> : DftOdd<3, INV> {};
 template <bool INV> struct Dft<5, INV> : DftOdd<5, INV> {};
 template <bool INV> struct Dft<7, INV> : DftOdd<7, INV> {};
 
-// x / d and x % d for 0 <= x < 2^24, 1 <= d < 2^16: the FP32 quotient is
-// off by at most one, fixed with one correction.
+// x / d and x % d for 0 <= x < 2^24, 1 <= d < 2^16: a shift and a mask when
+// d is a power of two (a uniform branch), else the FP32 quotient, off by at
+// most one, fixed with one correction.
 struct FastDiv {
     float r;
     int d;
+    int sh;        // log2 d when d is a power of two, else -1
 };
-__device__ __forceinline__ FastDiv fastdiv(int d) { return {1.0f / (float)d, d}; }
+__device__ __forceinline__ FastDiv fastdiv(int d)
+{
+    const int sh = ((d & (d - 1)) == 0) ? __ffs(d) - 1 : -1;
+    return {1.0f / (float)d, d, sh};
+}
 __device__ __forceinline__ int fdivmod(int x, FastDiv f, int& rem)
 {
+    if (f.sh >= 0) {
+        rem = x & (f.d - 1);
+        return x >> f.sh;
+    }
     int q = (int)((float)x * f.r);
     int r = x - q * f.d;
     if (r < 0) {
