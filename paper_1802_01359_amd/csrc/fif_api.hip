@@ -486,7 +486,7 @@ fif_status fif_plan_create(fif_plan** out, const int64_t* lengths, int32_t B, in
     // signal groups of about equal sample counts
     {
         const char* env = getenv("FIF_GROUPS");
-        int G = env ? atoi(env) : 2;
+        int G = env ? atoi(env) : 4;
         G = std::max(1, std::min(G, std::min(B, 8)));
         int64_t total = 0;
         for (int32_t b = 0; b < B; ++b) total += lengths[b];

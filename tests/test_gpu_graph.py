@@ -82,3 +82,26 @@ def test_graph_replays_fp64():
             stream.synchronize()
             assert _same(out, ref), "replay %d" % rep
             _ = (x * 3.0).sum().item()
+
+
+def test_graph_replays_with_a_sampled_window():
+    """The per-step eigenvalue tables (taps, forward transform) are part of
+    the captured graph too."""
+    lengths = [65536] * 2 + [4096, 131072, 1000]
+    sig = [siggen.chirps(i) if n == 65536 else siggen.uneven_signal(i, n) for i, n in enumerate(lengths)]
+    print("graph window lengths %s" % lengths, flush=True)
+    x = torch.tensor(np.concatenate(sig), dtype=torch.float32).cuda()
+    shape = list(0.5 * (1.0 + np.cos(np.pi * np.arange(17) / 16)))
+    plan = fif.Plan(lengths, 6, fif.Options(window=shape, gamma=1e-3))
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ref = plan.run(x, 1e-3)
+        stream.synchronize()
+        out = plan.alloc_outputs(torch.float32)
+        for rep in range(3):
+            out.imfs.fill_(3.0)
+            plan.run(x, 1e-3, out=out, graph=True)
+            stream.synchronize()
+            assert _same(out, ref), "replay %d" % rep
+            _ = (x * 3.0).sum().item()
+            stream.synchronize()
