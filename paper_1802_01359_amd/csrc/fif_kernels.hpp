@@ -308,6 +308,7 @@ __device__ __forceinline__ int64_t mulmod53(int64_t a, int64_t b, int64_t n, dou
 // Window spectrum of one plan length at the current L.
 struct Lam {
     int64_t N, Lmod;
+    int64_t mask;         // N - 1 when N is a power of two (L j mod N by a mask), else 0
     double invN, invL;
     const double* sinT;   // sin(pi u/N), u <= N/2
     const double* isinT;  // 1/sin(pi u/N), 1 <= u <= N/2
@@ -318,6 +319,7 @@ __device__ __forceinline__ Lam make_lam(const LenPlan& lp, const double* dtab, i
 {
     Lam w;
     w.tab = tab;
+    w.mask = ((lp.N & (lp.N - 1)) == 0) ? lp.N - 1 : 0;
     w.N = lp.N;
     w.Lmod = L % lp.N;
     w.invN = lp.invN;
@@ -334,7 +336,7 @@ __device__ __forceinline__ double lambda_at(int64_t j, const Lam& w)
 {
     if (j == 0) return 1.0;
     if (w.tab) return w.tab[j];
-    int64_t t = mulmod53(w.Lmod, j, w.N, w.invN);
+    int64_t t = w.mask ? ((w.Lmod * j) & w.mask) : mulmod53(w.Lmod, j, w.N, w.invN);
     if (t > w.N - t) t = w.N - t;
     const double q = w.sinT[t] * w.isinT[j] * w.invL;
     const double q2 = q * q;
