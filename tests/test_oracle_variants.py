@@ -229,3 +229,25 @@ def test_two_tones_cross_over_where_the_closed_form_says():
         m += 1
     assert m > 1000 and d.m[0] == m
     assert fs.decompose(s, delta, 1, mask_rule=1).m[0] == m     # linear scan alike
+
+
+def test_noise_floor_and_rescaling_leave_ordinary_signals_alone():
+    """On signals whose SD crosses delta long before any weight underflows,
+    the noise floor and the rescaled sums give the plain N0 = 1, 2, ... scan
+    of equation "SD" (written out here without either)."""
+    for s in (siggen.tones3(N=2048), siggen.chirps(5, N=4096), siggen.uneven_signal(9, 3000)):
+        d = fs.decompose(s, 1e-3, 1)
+        N = s.size
+        R = np.fft.fft(s)
+        lam = fs.eigenvalues_closed(N, d.L[0])
+        P = np.abs(R) ** 2
+        x = P.copy()
+        m = 0
+        while True:
+            m += 1
+            sd = math.sqrt(float(np.sum(x * lam * lam)) / float(np.sum(x)))
+            if sd <= 1e-3:
+                break
+            x = x * (1.0 - lam) ** 2
+        assert d.m[0] == m
+        assert d.sd[0] == pytest.approx(sd, rel=1e-9)
