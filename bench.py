@@ -335,14 +335,21 @@ def main():
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kind,
                     "algorithmic_bytes_per_launch": alg_per_launch, "avg_launch_ms": round(avg_ms, 4),
                     "kernel_share_of_step": round(ms / tot_ms, 3)}
+        if traffic is not None:
+            # measured HBM bytes of the same launches over their duration
+            tg = traffic / (avg_ms * 1e-3) / 1e9
+            roofline["traffic_GBs"] = round(tg, 1)
+            roofline["traffic_frac"] = round(tg / HBM_PEAK_GBS, 4)
 
     value = total * args.steps / el
+    # I/O floor: read the signals, write max_imfs IMF rows and the remainders
+    io_floor = (J + 2) * total * esize * args.steps / el / 1e9
     res = {
         "metric": METRIC, "value": value, "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": W["workload"], "signals": len(lengths), "samples": total, "delta": delta,
-                   "max_imfs": J, "io_dtype": W["io"],
+                   "max_imfs": J, "io_dtype": W["io"], "io_floor_GBs": round(io_floor, 1),
                    "launch": "hip graph replay" if (args.graph and args.workload != "plain")
                    else "stream",
                    "form": "plain single-signal" if args.workload == "plain" else
