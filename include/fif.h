@@ -94,7 +94,13 @@ typedef struct {
                             bin 1 <= f <= N/2 whose power is >= peak_rho times
                             the strongest of those bins (the spectral-peak rule
                             of Section 2) */
-    int32_t stop_mode;   /* 0: smallest m with SD_m <= delta (equation "SD")
+    int32_t stop_mode;   /* 0: smallest m with SD_m <= delta (equation "SD");
+                               SD counts the bins with |R_j|^2 >= 1e-26 times
+                               the strongest non-constant bin's (the rest is
+                               rounding-level content) and is summed relative
+                               to its largest weight, so a residual whose
+                               counted bins all have lambda > delta (a pure
+                               tone, for one) runs to max_inner (FIF_IMF_CAP)
                             1: smallest m >= 1 with ||s_{m+1} - s_m||_2 < delta
                                (equation "Discrete_Abs_StopCond"), IMF = s_m
                             2: m = N0, the smallest N0 >= 1 satisfying
