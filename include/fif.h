@@ -208,6 +208,28 @@ fif_status fif_decompose_batched_graph_f64(fif_plan* plan, const double* signals
                                            void* workspace, void* stream);
 
 /*
+ * fif_decompose_batched without a workspace argument and without any
+ * allocation, for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid it).  The
+ * workspace is a fixed array of FIF_STATIC_WORKSPACE_BYTES inside the
+ * library, one copy per device, held from the library's load until the
+ * process ends.  The call allocates nothing, creates no stream or event,
+ * and issues every kernel on `stream` (the signal groups of the batched
+ * call run one after another there).  Plans whose workspace
+ * (fif_plan_workspace_size) exceeds FIF_STATIC_WORKSPACE_BYTES are
+ * refused with FIF_ERR_CAPACITY; a plan with profiling enabled is refused
+ * with FIF_ERR_INVALID_ARG.  Every call on one device shares that device's
+ * array: calls that overlap in time on one device (two streams, two host
+ * threads) race and give wrong results.  Each call writes every workspace
+ * word before reading it, so nothing has to be cleared between calls.
+ * Results equal fif_decompose_batched's.
+ */
+#define FIF_STATIC_WORKSPACE_BYTES (64u << 20)
+fif_status fif_decompose_batched_static(fif_plan* plan, const float* signals, double delta,
+                                        float* imfs, float* remainders, int32_t* n_imfs,
+                                        fif_imf_info* info, int32_t* sig_status, void* stream);
+
+/*
  * Plain single-signal form: one signal of length N, one IMF per host
  * iteration, the host reads the signal's state after every outer step and
  * stops launching once it has finished.  The library allocates and caches

@@ -18,7 +18,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from ._binding import (EXPORTED, IMF_CAP, IMF_INFO_DTYPE, IMF_REFINED, NET_CHANNELS, NET_FEATURES, NET_PARAMS,
+from ._binding import (EXPORTED, IMF_CAP, STATIC_WORKSPACE_BYTES, IMF_INFO_DTYPE, IMF_REFINED, NET_CHANNELS, NET_FEATURES, NET_PARAMS,
                        FifError, Options, check, load, LIB_PATH, STOP_FAILED, STOP_FEW_EXTREMA, STOP_FLOOR,
                        STOP_MAX_IMFS)
 
@@ -211,6 +211,25 @@ class Plan:
                 else lib.fif_decompose_batched_graph_f64
         check(fn(self._h, _ptr(signals), float(delta), _ptr(out.imfs), _ptr(out.remainders), _ptr(out.n_imfs),
                  _ptr(out.info_raw) if with_info else 0, _ptr(out.sig_status), aligned, _stream_ptr(torch)))
+        return out
+
+
+    def run_static(self, signals, delta: float, out: BatchResult | None = None,
+                   with_info: bool = True) -> BatchResult:
+        """fif_decompose_batched_static: the batched decomposition with the
+        library's static workspace (no allocation inside the call; FP32;
+        plans needing more than STATIC_WORKSPACE_BYTES are refused)."""
+        torch = _torch()
+        lib = load()
+        if signals.dtype != torch.float32 or signals.dim() != 1 or signals.numel() != self.total \
+                or not signals.is_cuda or not signals.is_contiguous():
+            raise ValueError("signals must be a contiguous 1-D CUDA float32 tensor of %d samples" % self.total)
+        if out is None:
+            out = self.alloc_outputs(signals.dtype)
+        check(lib.fif_decompose_batched_static(self._h, _ptr(signals), float(delta), _ptr(out.imfs),
+                                               _ptr(out.remainders), _ptr(out.n_imfs),
+                                               _ptr(out.info_raw) if with_info else 0, _ptr(out.sig_status),
+                                               _stream_ptr(torch)))
         return out
 
 

@@ -23,6 +23,9 @@ FIF_ERR_DEVICE = -4
 FIF_ERR_NONFINITE = -5
 FIF_ERR_CAPACITY = -6
 
+# size of the library's static workspace (fif_decompose_batched_static)
+STATIC_WORKSPACE_BYTES = 64 << 20
+
 IMF_CAP = 1
 IMF_REFINED = 2
 
@@ -38,7 +41,7 @@ EXPORTED = (
     "fif_model_create", "fif_model_free", "fif_model_get_params", "fif_model_set_params",
     "fif_model_save", "fif_model_load", "fif_model_forward", "fif_model_grad", "fif_model_train_step",
     "fif_plan_set_proposal", "fif_plan_record_features", "fif_decompose_batched_graph",
-    "fif_decompose_batched_graph_f64",
+    "fif_decompose_batched_graph_f64", "fif_decompose_batched_static",
 )
 
 NET_FEATURES = 1024
@@ -119,6 +122,8 @@ def load():
         f = getattr(lib, name)
         f.restype = ctypes.c_int
         f.argtypes = [vp, vp, dbl, vp, vp, vp, vp, vp, vp, vp]
+    lib.fif_decompose_batched_static.restype = ctypes.c_int
+    lib.fif_decompose_batched_static.argtypes = [vp, vp, dbl, vp, vp, vp, vp, vp, vp]
     for name in ("fif_decompose", "fif_decompose_f64"):
         f = getattr(lib, name)
         f.restype = ctypes.c_int

@@ -1010,9 +1010,11 @@ fif_status group_streams(fif_plan* p)
     return FIF_OK;
 }
 
+// one_stream: every signal group on the caller's stream (no group streams or
+// events are created), for the entry point that allocates nothing.
 template <typename T>
 fif_status batched(fif_plan* p, const T* x, double delta, T* imfs, T* rem, int32_t* n_imfs, fif_imf_info* info,
-                   int32_t* sig_status, void* ws, void* stream)
+                   int32_t* sig_status, void* ws, void* stream, bool one_stream = false)
 {
     g_err.clear();
     if (!p) return fail(FIF_ERR_INVALID_ARG, "plan is null");
@@ -1029,7 +1031,7 @@ fif_status batched(fif_plan* p, const T* x, double delta, T* imfs, T* rem, int32
     // to the caller's stream); a single group when the proposal network or
     // feature recording is on (they share buffers across signals) or while
     // profiling (each kernel then runs alone and its events time it alone)
-    const int G = (p->model || p->rec || p->prof) ? 1 : (int)p->groups.size();
+    const int G = (p->model || p->rec || p->prof || one_stream) ? 1 : (int)p->groups.size();
     if (G <= 1) {
         for (int t = 0; t < p->max_imfs; ++t) launch_step<T>(p, b, t, x, imfs, ws, s, p->all);
     } else {
@@ -1047,6 +1049,42 @@ fif_status batched(fif_plan* p, const T* x, double delta, T* imfs, T* rem, int32
     }
     launch_final<T>(p, b, x, rem, n_imfs, sig_status, info, s);
     HIP_TRY(hipGetLastError());
+    return FIF_OK;
+}
+
+// ------------------------------------------- entry point without allocation
+
+// Workspace of fif_decompose_batched_static: a fixed array in the library's
+// code object.  Every device the library runs on holds its own copy until
+// the process ends; host code reaches it only through the address
+// hipGetSymbolAddress returns for the current device (the array's name is a
+// host-side stand-in, not a device address).
+static __device__ __align__(256) unsigned char scratch[FIF_STATIC_WORKSPACE_BYTES];
+
+struct ScratchAddrs {
+    std::mutex mu;
+    std::map<int, void*> ptr;      // device -> address of its copy of scratch
+};
+ScratchAddrs& scratch_addrs()
+{
+    static ScratchAddrs* a = new ScratchAddrs();
+    return *a;
+}
+
+// Address of the current device's copy of scratch, looked up once per device.
+fif_status scratch_ptr(int dev, void** out)
+{
+    auto& A = scratch_addrs();
+    std::lock_guard<std::mutex> lock(A.mu);
+    auto it = A.ptr.find(dev);
+    if (it == A.ptr.end()) {
+        void* q = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !q)
+            return fail(FIF_ERR_DEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        it = A.ptr.emplace(dev, q).first;
+    }
+    *out = it->second;
     return FIF_OK;
 }
 
@@ -1223,6 +1261,26 @@ fif_status fif_decompose_batched_graph_f64(fif_plan* plan, const double* signals
                                            int32_t* sig_status, void* workspace, void* stream)
 {
     return batched_graph<double>(plan, signals, delta, imfs, remainders, n_imfs, info, sig_status, workspace, stream);
+}
+
+fif_status fif_decompose_batched_static(fif_plan* plan, const float* signals, double delta, float* imfs,
+                                        float* remainders, int32_t* n_imfs, fif_imf_info* info,
+                                        int32_t* sig_status, void* stream)
+{
+    g_err.clear();
+    if (!plan) return fail(FIF_ERR_INVALID_ARG, "plan is null");
+    if (plan->ws_total > (size_t)FIF_STATIC_WORKSPACE_BYTES)
+        return fail(FIF_ERR_CAPACITY, "plan needs %zu bytes of workspace; the static workspace holds %zu",
+                    plan->ws_total, (size_t)FIF_STATIC_WORKSPACE_BYTES);
+    if (plan->prof) return fail(FIF_ERR_INVALID_ARG, "profiling creates events: not with the static workspace");
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != plan->device)
+        return fail(FIF_ERR_INVALID_ARG, "plan was created on device %d, current is %d", plan->device, dev);
+    void* ws = nullptr;
+    const fif_status st = scratch_ptr(dev, &ws);
+    if (st != FIF_OK) return st;
+    return batched<float>(plan, signals, delta, imfs, remainders, n_imfs, info, sig_status, ws, stream, true);
 }
 
 fif_status fif_decompose(const float* signal, int64_t N, fif_window window, double delta, int32_t max_imfs,
