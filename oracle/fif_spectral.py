@@ -37,7 +37,7 @@ of the sums; and the sums are taken scale-free, every weight divided by the
 largest, so that they never underflow.  Without either, a pure tone whose
 lambda exceeds delta (SD constant, the case the iteration cap exists for)
 would stop wherever the tone's power underflows or the noise takes over.
-  - window=shape: another window than the triangle of equation 271.  Section
+  - window=shape: another window than the triangle of equation "triangular".  Section
     4 only needs W's eigenvalues, the DFT of its first column (equation
     "Lambdas"), which can be tabulated for any filter.  Read here as: h, the
     non-negative samples `shape` (at x = i/K, i = 0..K) linearly
@@ -182,6 +182,28 @@ def peak_frequency(R, rho: float) -> int:
     top = float(P.max()) if P.size else 0.0
     idx = np.flatnonzero(P >= rho * top)
     return int(idx[-1]) + 1 if idx.size and top > 0 else 1
+
+
+def imfs_at(s, Ls, ms, gamma: float = 0.0):
+    """IMFs and remainder of the direct form (Theorem 5, equation
+    "IMF1_direct"; Section 4, equation "One step_algo") at given mask
+    lengths Ls[j] and step counts ms[j], without the search for m: IMF_j =
+    IDFT((1 - lambda)^m_j DFT(r_j)), r_{j+1} = r_j - IMF_j.  The signal is
+    real, so the half spectrum (numpy's real FFT) carries the same
+    computation at half the cost; it lets a test rebuild long decompositions
+    whose decisions were stored."""
+    r = np.ascontiguousarray(np.asarray(s, dtype=np.float64)).copy()
+    N = r.size
+    imfs = []
+    for L, m in zip(Ls, ms):
+        R = np.fft.rfft(r)
+        g = _pow1m(eigenvalues_closed(N, int(L))[:R.size], int(m))
+        if gamma > 0.0:
+            g = np.where(g >= 1.0 - gamma, 1.0, g)
+        imf = np.fft.irfft(g * R, n=N)
+        imfs.append(imf)
+        r = r - imf
+    return (np.array(imfs) if imfs else np.zeros((0, N))), r
 
 
 def decompose(s, delta: float, max_imfs: int, *, mask_rule: int = 0, nu: float = 1.6,

@@ -253,8 +253,10 @@ def test_exact_rational_decisions(seed):
 
 @pytest.fixture(scope="module")
 def tones_dec():
+    """The three-tone signal decomposed by the literal iteration (folded
+    taps, one tap sum per output sample; about 4 s)."""
     s = siggen.tones3()
-    return s, dif.decompose(s, 1e-3, 8)
+    return s, dif.decompose(s, 1e-3, 8, inner_form=0)
 
 
 def test_reconstruction_and_zero_mean(tones_dec):
@@ -274,15 +276,21 @@ def test_three_tones_separate(tones_dec):
              for f, sg in ((200, 1), (40, -1), (8, 1))]
     for imf, c in zip(d.imfs[:3], comps):
         assert np.corrcoef(imf, c)[0, 1] > 0.999
-    assert d.k[:3] == [401, 79, 16]
-    assert d.L[:3] == [21, 104, 512]
+    # a residual led by a tone of f cycles has about 2f extrema (one maximum
+    # and one minimum per cycle); the mask length then follows its rule
+    for kj, Lj, f in zip(d.k[:3], d.L[:3], (200, 40, 8)):
+        assert abs(kj - 2 * f) <= 2, (kj, f)
+        assert Lj == -(-2 * s.size // kj)
     assert all(sd <= 1e-3 for sd in d.sd)
     assert all(p > 1e-3 for p in d.sd_prev)
 
 
 def test_literal_and_box_oracles_agree(tones_dec):
+    """The literal folded-tap iteration and the four-box-sum form of W give
+    the same decomposition of the three-tone signal (N = 4096)."""
     s, d = tones_dec
     e = dif.decompose(s, 1e-3, 8, inner_form=1)
+    assert d.n_imfs == e.n_imfs >= 4
     assert (d.k, d.L, d.m) == (e.k, e.L, e.m)
     scale = np.linalg.norm(s)
     for a, b in zip(d.imfs, e.imfs):
@@ -369,3 +377,50 @@ def test_mask_rules():
     assert dif.mask_length(10, 3, 0) == 7
     assert dif.mask_length(4096, 401, 1, 1.6) == 2 * math.floor(1.6 * 4096 / 401)
     assert dif.mask_length(100, 7, 1, 1.6) == 44
+
+
+def test_degenerate_tail_time_domain_stops_at_the_rounding_level():
+    """A pure tone whose eigenvalue exceeds delta: in exact arithmetic every
+    iterate is the tone times (1 - lambda)^m, so SD_m = lambda > delta for
+    every m and the inner loop can only end at the cap (equation "SD", the
+    cap stated beside it).  The FP64 time-domain iteration keeps SD = lambda
+    while the tone is representable, then stops once the tone has decayed to
+    the rounding level of the signal, at a step count that depends on the
+    order of the roundings (literal taps and box sums differ).  The direct
+    form with the noise-floor reading returns the cap, the exact-arithmetic
+    answer; that reading decides on such tails."""
+    N, k0, delta = 256, 8, 5e-4
+    s = np.cos(2 * np.pi * k0 * np.arange(N) / N + 0.3)
+    lit = dif.decompose(s, delta, 1, mask_rule=1, inner_form=0)
+    box = dif.decompose(s, delta, 1, mask_rule=1, inner_form=1)
+    spec = fif_spectral.decompose(s, delta, 1, mask_rule=1)
+    assert lit.L == box.L == spec.L
+    lam = closed_form_lambda(N, lit.L[0])[k0]
+    assert lam > delta
+    # exact answer: the cap, SD = lambda
+    assert spec.m == [1_000_000] and spec.flags == [dif.FLAG_CAP]
+    assert abs(spec.sd[0] - lam) <= 1e-15
+    # time domain: SD = lambda to rounding for the first 2000 steps ...
+    _, sd, _ = dif.inner_trace(s, lit.L[0], 2000, form=1)
+    assert np.max(np.abs(sd - lam)) < 1e-15
+    # ... and its stop comes only where the exact iterate (1 - lambda)^m has
+    # fallen below 1e-15 of the tone, at a rounding-dependent m
+    for d in (lit, box):
+        assert d.m[0] < 1_000_000 and d.flags == [0]
+        assert (1.0 - lam) ** d.m[0] < 1e-15
+        assert (1.0 - lam) ** (d.m[0] - 2000) > 1e-15
+    assert lit.m != box.m
+
+
+def test_imfs_at_given_decisions_repeat_the_decomposition():
+    """fif_spectral.imfs_at with the (L, m) the direct form chose gives its
+    IMFs and remainder (the same formula on the half spectrum: equal up to
+    FFT rounding)."""
+    s = siggen.tones3(N=2048, freqs=(6, 31, 150), seed_index=9)
+    d = fif_spectral.decompose(s, 1e-3, 6)
+    imfs, rem = fif_spectral.imfs_at(s, d.L, d.m)
+    sn = np.linalg.norm(s)
+    assert imfs.shape == d.imfs.shape
+    for a, b in zip(imfs, d.imfs):
+        assert np.linalg.norm(a - b) <= 1e-14 * sn
+    assert np.linalg.norm(rem - d.remainder) <= 1e-14 * sn
