@@ -48,6 +48,7 @@ METRIC = "signal samples decomposed/sec (FP32 batched FIF) vs plain, % HBM peak"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 MODEL_FILE = os.path.join(ROOT, "paper_1802_01359_amd", "data", "proposal_tones3_65536.fifnet")
+TUNE_CACHE = os.path.join(ROOT, "paper_1802_01359_amd", "data", "tune_cache.txt")
 
 
 def log(*a):
@@ -148,31 +149,73 @@ def algorithmic_bytes(kind: str, lengths, n_imfs, max_imfs: int, esize: int) -> 
     return 0.0                                              # bookkeeping / implementation-only kernels
 
 
-def cpu_baseline(sigs, delta, max_imfs, want: int, budget_s: float, threads: int, window=None, okw=None):
-    """The oracle, one signal per host thread (the C oracle releases the GIL),
-    over rounds of `threads` signals until `want` signals or the budget.  A
-    sampled window shape or a variant runs the FP64 spectral oracle (numpy)
-    instead, the time-domain one having only the plain method."""
+def host_cores() -> int:
+    """Host threads to give the CPU oracle: OMP_NUM_THREADS when the
+    environment sets it (a host that shares its cores between jobs states
+    this job's share that way), else every core this process may run on."""
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        return int(env)
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(sigs, delta, max_imfs, count: int, threads: int, window=None, okw=None, spectral=False):
+    """The oracle on the first `count` signals, one signal per host thread
+    (the C oracle releases the GIL; numpy's FFT does too) until all are
+    done.  Returns (decompositions, samples, wall seconds).  A sampled window
+    shape or a variant runs the FP64 spectral oracle (numpy), the
+    time-domain one having only the plain method; spectral=True asks for it
+    as well."""
     from concurrent.futures import ThreadPoolExecutor
     from oracle import dif
     from oracle import fif_spectral
 
     def one(s):
         s = np.asarray(s, dtype=np.float64)
-        if window is not None or okw:
+        if spectral or window is not None or okw:
             return fif_spectral.decompose(s, delta, max_imfs, window=window, **(okw or {}))
         return dif.decompose(s, delta, max_imfs)
+    batch = sigs[:count]
     t0 = time.perf_counter()
-    done = 0
-    samples = 0
     with ThreadPoolExecutor(max_workers=threads) as ex:
-        while done < min(want, len(sigs)) and time.perf_counter() - t0 < budget_s:
-            batch = sigs[done:min(want, len(sigs), done + threads)]
-            list(ex.map(one, batch))
-            done += len(batch)
-            samples += sum(len(s) for s in batch)
+        decs = list(ex.map(one, batch))
     el = time.perf_counter() - t0
-    return done, samples, el
+    return decs, sum(len(s) for s in batch), el
+
+
+def parity_of(decs, sigs, out, J, esize):
+    """Decisions and per-IMF relative L2 error of the GPU output `out` for the
+    signals the CPU oracle decomposed (signal b = decs[b])."""
+    info = out.info()
+    n = out.n_imfs.cpu().numpy()
+    same = 0
+    worst = 0.0
+    for b, d in enumerate(decs):
+        nb = int(n[b])
+        got = [(int(info["k"][b][j]), int(info["L"][b][j]), int(info["m"][b][j])) for j in range(nb)]
+        if nb == d.n_imfs and got == list(zip(d.k, d.L, d.m)):
+            same += 1
+            imfs = out.imfs_of(b).cpu().numpy().astype(np.float64)
+            for j in range(nb):
+                a = d.imfs[j]
+                na = float(np.linalg.norm(a))
+                if na > 0:
+                    worst = max(worst, float(np.linalg.norm(a - imfs[j])) / na)
+    return {"signals": len(decs), "decisions_identical": same, "max_imf_rel_l2": worst}
 
 
 def main():
@@ -183,12 +226,19 @@ def main():
     ap.add_argument("--workload", default="chirps", choices=["chirps", "uneven", "long", "tones3", "plain", "learned", "window"])
     ap.add_argument("--variant", default=None, choices=sorted(VARIANTS), help="a variant of the method (see above)")
     ap.add_argument("--model", default=MODEL_FILE, help="proposal network file (learned workload)")
-    ap.add_argument("--cpu-signals", type=int, default=8, help="signals the CPU oracle decomposes at most")
-    ap.add_argument("--cpu-threads", type=int, default=1,
-                    help="host threads for the oracle (it is memory bound: more than two threads slow it down)")
-    ap.add_argument("--cpu-budget", type=float, default=25.0, help="seconds of CPU oracle work at most")
+    ap.add_argument("--cpu-signals", type=int, default=0,
+                    help="signals the CPU oracle decomposes (default: two per host thread)")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="host threads for the oracle (default: OMP_NUM_THREADS, else every usable core)")
+    ap.add_argument("--plain-signals", type=int, default=64,
+                    help="signals of the batch timed through the plain single-signal form (headline workload)")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="headline workload: skip timing the plain single-signal and learned-proposal forms")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", action="store_true", help="time replays of a captured HIP graph (FP32 workloads)")
+    ap.add_argument("--tune-cache", default=TUNE_CACHE,
+                    help="autotuner cache file (lengths missing from it are timed when the plan is created)")
+    ap.add_argument("--no-tune", action="store_true", help="built-in split, tiles and radix order for every length")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 512 MiB device copy first (a known-size kernel to scale HBM counters by)")
     args = ap.parse_args()
@@ -228,6 +278,8 @@ def main():
 
     roofline = None
     extra = {}
+    forms = {}
+    plans = {}
     if args.workload == "plain":
         # plain single-signal form, one signal after another, host loop per outer step
         N = lengths[0]
@@ -246,7 +298,21 @@ def main():
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
     else:
-        plan = fif.Plan(lengths, J, fif.Options(window=W.get("window"), **lib_opt))
+        t_plan = time.perf_counter()
+        plan = fif.Plan(lengths, J, fif.Options(window=W.get("window"), **lib_opt),
+                        tune_cache=None if args.no_tune else args.tune_cache)
+        t_plan = time.perf_counter() - t_plan
+        plans = {"tuned": not args.no_tune, "create_s": round(t_plan, 2)}
+        if not args.no_tune:
+            chosen = [plan.length_plan(int(N)) for N in sorted(set(int(v) for v in lengths)) if N > 8192]
+            timed = [c for c in chosen if c["us"] > 0 and c["us_default"] > 0]
+            plans["lengths_tuned"] = len(timed)
+            if timed:
+                plans["builtin_over_tuned_time"] = round(float(np.exp(np.mean(
+                    [np.log(c["us_default"] / c["us"]) for c in timed]))), 4)
+            if len(chosen) <= 4:
+                plans["choices"] = [{k: c[k] for k in ("N", "N1", "N2", "TC", "TR", "rad1", "rad2")} for c in chosen]
+            log("plans: %s" % plans)
         out = plan.alloc_outputs(dt)
         model = None
         if args.workload == "learned":
@@ -274,6 +340,44 @@ def main():
         torch.cuda.synchronize()
         prof = plan.profile_read()
         plan.profile(False)
+        forms = {}
+        if args.workload == "chirps" and not args.variant and not args.no_forms:
+            # the same batch through the plain single-signal form (a host
+            # loop per outer step, one signal after another) on its first
+            # signals, and through the batched form with the learned proposal
+            N = lengths[0]
+            P = min(args.plain_signals, len(lengths))
+            fif.decompose(packed[:N], delta, J)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for b in range(P):
+                fif.decompose(packed[b * N:(b + 1) * N], delta, J)
+            torch.cuda.synchronize()
+            el_p = time.perf_counter() - t1
+            forms["plain_form"] = {"value": P * N / el_p, "signals": P, "ms_per_signal": 1e3 * el_p / P}
+            lmodel = fif.Model(path=args.model, max_batch=len(lengths))
+            plan.set_proposal(lmodel)
+            lo = plan.alloc_outputs(dt)
+            plan.run(packed, delta, out=lo)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(args.steps):
+                plan.run(packed, delta, out=lo)
+            torch.cuda.synchronize()
+            el_l = time.perf_counter() - t1
+            plan.set_proposal(None)
+            li, oi = lo.info(), out.info()
+            lm = np.arange(J)[None, :] < lo.n_imfs.cpu().numpy()[:, None]
+            forms["learned_form"] = {
+                "value": total * args.steps / el_l, "ms_per_step": 1e3 * el_l / args.steps,
+                "identical_to_plain_search": bool(torch.equal(lo.imfs, out.imfs) and torch.equal(lo.n_imfs, out.n_imfs)
+                                                  and np.array_equal(li["m"], oi["m"])
+                                                  and np.array_equal(li["L"], oi["L"])),
+                "fp32_passes_per_imf": float((li["evals"][lm] & 0xffff).mean()),
+                "model": os.path.basename(args.model)}
+            log("plain single-signal form %.3g samples/s, learned proposal %.3g samples/s (identical %s)" % (
+                forms["plain_form"]["value"], forms["learned_form"]["value"],
+                forms["learned_form"]["identical_to_plain_search"]))
         extra = {}
         if model is not None:
             # the same batch with the plain search, for comparison
@@ -356,6 +460,11 @@ def main():
                    ("batched, learned proposal of m" if args.workload == "learned" else
                     ("batched, sampled window shape" if args.workload == "window" else "batched"))},
     }
+    if args.workload != "plain":
+        res["config"]["plans"] = plans
+    if args.workload != "plain" and forms:
+        res["config"].update(forms)
+        res["config"]["vs_plain"] = value / forms["plain_form"]["value"]
     if args.variant:
         res["config"]["variant"] = {"name": args.variant, "options": lib_opt}
     if args.workload not in ("plain",) and extra:
@@ -363,16 +472,25 @@ def main():
     if roofline is not None:
         res["roofline"] = roofline
     if not args.no_cpu_baseline:
-        threads = max(1, args.cpu_threads)
-        done, samples, cel = cpu_baseline(sigs, delta, J, args.cpu_signals, args.cpu_budget, threads,
-                                          W.get("window"), oracle_opt)
+        threads = args.cpu_threads if args.cpu_threads > 0 else host_cores()
+        count = args.cpu_signals if args.cpu_signals > 0 else 2 * threads
+        count = min(count, len(sigs))
+        spectral = bool(W.get("window") or oracle_opt)
+        log("CPU oracle: %d signals on %d threads ..." % (count, threads))
+        decs, samples, cel = cpu_baseline(sigs, delta, J, count, threads, W.get("window"), oracle_opt)
         res["cpu_baseline"] = {
             "value": samples / cel, "unit": "samples/s", "cores": threads, "kind": "oracle",
-            "sample": "first %d of %d signals of the same workload, full decomposition by the FP64 "
-                      "%s oracle, one signal per thread, %d threads, %.1f s" % (
-                          done, len(lengths),
-                          "spectral (numpy)" if (W.get("window") or oracle_opt) else "time-domain (C)",
-                          threads, cel)}
+            "sample": "first %d of %d signals of the same workload, whole decompositions by the FP64 %s oracle, "
+                      "one signal per thread, %d threads, %.1f s wall" % (
+                          count, len(lengths), "spectral (numpy)" if spectral else "time-domain (C)", threads, cel),
+            "nproc": os.cpu_count(), "cpu_model": cpu_model()}
+        if args.workload != "plain":
+            res["cpu_baseline"]["gpu_parity_on_sample"] = parity_of(decs, sigs, out, J, esize)
+        if not spectral and args.workload in ("chirps", "uneven"):
+            # context: the FP64 direct form (numpy FFT) on the same signals
+            _, s2, c2 = cpu_baseline(sigs, delta, J, count, threads, spectral=True)
+            res["cpu_baseline"]["spectral_oracle_value"] = s2 / c2
+        log("CPU oracle: %.3g samples/s" % res["cpu_baseline"]["value"])
     print(json.dumps(res), flush=True)
 
 

@@ -66,7 +66,8 @@ typedef enum {
     FIF_ERR_NOMEM = -3,
     FIF_ERR_DEVICE = -4,
     FIF_ERR_NONFINITE = -5,  /* only ever stored in sig_status[] */
-    FIF_ERR_CAPACITY = -6
+    FIF_ERR_CAPACITY = -6,
+    FIF_ERR_NOT_FOUND = -7   /* tune-cache lookup without an entry */
 } fif_status;
 
 typedef enum {
@@ -104,8 +105,8 @@ typedef struct {
                             1: smallest m >= 1 with ||s_{m+1} - s_m||_2 < delta
                                (equation "Discrete_Abs_StopCond"), IMF = s_m
                             2: m = N0, the smallest N0 >= 1 satisfying
-                               inequality "N0_discrete" of Theorem 5 (no search)
-                            modes 1 and 2 need every length <= 65536 */
+                               inequality "N0_discrete" of Theorem 5 (no search);
+                               mode 1 searches no count above that N0 */
     double nu;           /* mask_rule 1 constant, default 1.6 */
     int64_t max_inner;   /* cap on m, default 1000000 */
     double floor_tau;    /* rounding floor, default 1e-9 */
@@ -116,7 +117,7 @@ typedef struct {
     double peak_rho;     /* mask_rule 2 fraction, in (0, 1], default 0.1 */
     const double* window;/* HOST array of window_points >= 2 samples of a window
                             shape on [0, 1] (x_i = i / (window_points - 1)), or
-                            NULL (default): the triangle of equation 271 with the
+                            NULL (default): the triangle of equation "triangular" with the
                             closed-form eigenvalues of equation "eig2".  Section 4
                             needs only W's eigenvalues, the DFT of its first
                             column (equation "Lambdas"), so any shape can be
@@ -164,6 +165,54 @@ const char* fif_status_string(fif_status s);
  */
 fif_status fif_plan_create(fif_plan** plan, const int64_t* lengths, int32_t B, int32_t max_imfs,
                            const fif_options* opt);
+/*
+ * How one signal length is transformed: one LDS pass (N <= 8192: N1 = 1,
+ * N2 = N, TC = TR = 1), or the four-step split N = N1 * N2 whose pass 1
+ * transforms TC columns of length N2 per workgroup and pass 2 TR rows of
+ * length N1 (TC * N2 and TR * N1 at most 4096 elements), each length-n
+ * transform a sequence of radix passes (2, 3, 4, 5, 7 or 8, first pass
+ * first).  The FFT is what Section 4 makes the cost of each IMF; which
+ * split, tiles and radix order run fastest is a property of the device.
+ */
+typedef struct {
+    int64_t N;
+    int32_t N1, N2;        /* four-step split (N1 = 1 for one LDS pass) */
+    int32_t TC, TR;        /* columns per pass-1 tile, rows per pass-2 tile */
+    int32_t n_rad1, n_rad2;
+    int8_t rad1[24];       /* radices of the length-N2 transforms */
+    int8_t rad2[24];       /* radices of the length-N1 transforms (none: n_rad2 = 0) */
+    double us;             /* tuned plans: measured time of this choice (us), else 0 */
+    double us_default;     /* tuned plans: measured time of the built-in choice, else 0 */
+} fif_length_plan;
+
+/*
+ * fif_plan_create with plans picked by measurement.  For every distinct
+ * length above 8192 the library times candidate choices -- the three most
+ * balanced splits N1 * N2, the widest pass-1 and pass-2 tiles and half of
+ * each, the built-in radix order and its reverse; the built-in choice is
+ * one of them -- by decomposing a synthetic batch of that length (two IMFs)
+ * with each, and keeps the fastest.  Results are cached in the text file
+ * tune_cache (NULL: the file named by the environment variable
+ * FIF_TUNE_CACHE; NULL and unset: no cache) under a key made of the
+ * device's architecture name and the HIP runtime version; cached lengths are
+ * not timed again.  Shorter lengths take the built-in choice.  Tuning
+ * allocates and runs kernels on the current device and synchronises it.
+ */
+fif_status fif_plan_create_tuned(fif_plan** plan, const int64_t* lengths, int32_t B, int32_t max_imfs,
+                                 const fif_options* opt, const char* tune_cache);
+/* The choice the plan uses for length N (FIF_ERR_NOT_FOUND if the plan has
+   no signal of that length). */
+fif_status fif_plan_length_plan(const fif_plan* plan, int64_t N, fif_length_plan* out);
+/* Host-only access to a tune cache file: the last valid entry for
+   (device_key, N), or FIF_ERR_NOT_FOUND; and storing one (entries of
+   other keys or lengths are kept, lines that are not valid entries are
+   dropped; FIF_ERR_INVALID_ARG for an invalid choice or an unwritable
+   file).  fif_device_tune_key writes the current device's key (at most
+   `cap` bytes with the terminating zero). */
+fif_status fif_tune_cache_lookup(const char* path, const char* device_key, int64_t N, fif_length_plan* out);
+fif_status fif_tune_cache_store(const char* path, const char* device_key, const fif_length_plan* choice);
+fif_status fif_device_tune_key(char* key, int32_t cap);
+
 /* Bytes of device workspace fif_decompose_batched needs for this plan. */
 fif_status fif_plan_workspace_size(const fif_plan* plan, size_t* bytes);
 fif_status fif_plan_destroy(fif_plan* plan);

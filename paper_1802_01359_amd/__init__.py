@@ -18,7 +18,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from ._binding import (EXPORTED, IMF_CAP, STATIC_WORKSPACE_BYTES, IMF_INFO_DTYPE, IMF_REFINED, NET_CHANNELS, NET_FEATURES, NET_PARAMS,
+from ._binding import (EXPORTED, IMF_CAP, STATIC_WORKSPACE_BYTES, LengthPlan, IMF_INFO_DTYPE, IMF_REFINED, NET_CHANNELS, NET_FEATURES, NET_PARAMS,
                        FifError, Options, check, load, LIB_PATH, STOP_FAILED, STOP_FEW_EXTREMA, STOP_FLOOR,
                        STOP_MAX_IMFS)
 
@@ -115,7 +115,10 @@ class BatchResult:
 class Plan:
     """fif_plan_create / fif_decompose_batched for a fixed list of lengths."""
 
-    def __init__(self, lengths, max_imfs: int, options: Options | None = None):
+    def __init__(self, lengths, max_imfs: int, options: Options | None = None, tune: bool = False,
+                 tune_cache: str | None = None):
+        """tune / tune_cache: fif_plan_create_tuned (measured choices of split,
+        tiles and radix order per length, cached in the file tune_cache)."""
         torch = _torch()
         lib = load()
         self.lengths = np.asarray(lengths, dtype=np.int64).ravel()
@@ -126,8 +129,12 @@ class Plan:
         self._h = ctypes.c_void_p()
         arr = (ctypes.c_int64 * len(self.lengths))(*[int(v) for v in self.lengths])
         opt = (options or Options()).c()
-        check(lib.fif_plan_create(ctypes.byref(self._h), arr, len(self.lengths), self.max_imfs,
-                                  ctypes.byref(opt)))
+        if tune or tune_cache is not None:
+            check(lib.fif_plan_create_tuned(ctypes.byref(self._h), arr, len(self.lengths), self.max_imfs,
+                                            ctypes.byref(opt), tune_cache.encode() if tune_cache else None))
+        else:
+            check(lib.fif_plan_create(ctypes.byref(self._h), arr, len(self.lengths), self.max_imfs,
+                                      ctypes.byref(opt)))
         sz = ctypes.c_size_t()
         check(lib.fif_plan_workspace_size(self._h, ctypes.byref(sz)))
         self.workspace_bytes = int(sz.value)
@@ -142,6 +149,13 @@ class Plan:
             except Exception:
                 pass
             self._h = None
+
+    def length_plan(self, N: int) -> dict:
+        """The split, tiles and radix orders the plan uses for length N (and
+        the measured times when it was tuned)."""
+        c = LengthPlan()
+        check(load().fif_plan_length_plan(self._h, int(N), ctypes.byref(c)))
+        return c.to_dict()
 
     def workspace(self):
         torch = _torch()
@@ -231,6 +245,27 @@ class Plan:
                                                _ptr(out.info_raw) if with_info else 0, _ptr(out.sig_status),
                                                _stream_ptr(torch)))
         return out
+
+
+def tune_cache_lookup(path: str, device_key: str, N: int) -> dict | None:
+    """The cached choice for (device_key, N) in the tune cache file, or None."""
+    from ._binding import FIF_ERR_NOT_FOUND
+    c = LengthPlan()
+    st = load().fif_tune_cache_lookup(path.encode(), device_key.encode(), int(N), ctypes.byref(c))
+    if st == FIF_ERR_NOT_FOUND:
+        return None
+    check(st)
+    return c.to_dict()
+
+
+def tune_cache_store(path: str, device_key: str, choice: dict) -> None:
+    check(load().fif_tune_cache_store(path.encode(), device_key.encode(), ctypes.byref(LengthPlan.from_dict(choice))))
+
+
+def device_tune_key() -> str:
+    buf = ctypes.create_string_buffer(256)
+    check(load().fif_device_tune_key(buf, 256))
+    return buf.value.decode()
 
 
 def release_cache() -> None:

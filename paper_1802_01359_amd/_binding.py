@@ -22,6 +22,7 @@ FIF_ERR_NOMEM = -3
 FIF_ERR_DEVICE = -4
 FIF_ERR_NONFINITE = -5
 FIF_ERR_CAPACITY = -6
+FIF_ERR_NOT_FOUND = -7
 
 # size of the library's static workspace (fif_decompose_batched_static)
 STATIC_WORKSPACE_BYTES = 64 << 20
@@ -42,6 +43,8 @@ EXPORTED = (
     "fif_model_save", "fif_model_load", "fif_model_forward", "fif_model_grad", "fif_model_train_step",
     "fif_plan_set_proposal", "fif_plan_record_features", "fif_decompose_batched_graph",
     "fif_decompose_batched_graph_f64", "fif_decompose_batched_static",
+    "fif_plan_create_tuned", "fif_plan_length_plan", "fif_tune_cache_lookup", "fif_tune_cache_store",
+    "fif_device_tune_key",
 )
 
 NET_FEATURES = 1024
@@ -60,6 +63,33 @@ class _Options(ctypes.Structure):
                 ("max_inner", ctypes.c_int64), ("floor_tau", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("peak_rho", ctypes.c_double), ("window", ctypes.c_void_p), ("window_points", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
+
+
+class LengthPlan(ctypes.Structure):
+    """fif_length_plan: how one signal length is transformed."""
+    _fields_ = [("N", ctypes.c_int64), ("N1", ctypes.c_int32), ("N2", ctypes.c_int32), ("TC", ctypes.c_int32),
+                ("TR", ctypes.c_int32), ("n_rad1", ctypes.c_int32), ("n_rad2", ctypes.c_int32),
+                ("rad1", ctypes.c_int8 * 24), ("rad2", ctypes.c_int8 * 24), ("us", ctypes.c_double),
+                ("us_default", ctypes.c_double)]
+
+    def to_dict(self) -> dict:
+        return {"N": int(self.N), "N1": int(self.N1), "N2": int(self.N2), "TC": int(self.TC), "TR": int(self.TR),
+                "rad1": [int(self.rad1[i]) for i in range(self.n_rad1)],
+                "rad2": [int(self.rad2[i]) for i in range(self.n_rad2)], "us": float(self.us),
+                "us_default": float(self.us_default)}
+
+    @classmethod
+    def from_dict(cls, d: dict) -> "LengthPlan":
+        c = cls()
+        c.N, c.N1, c.N2, c.TC, c.TR = int(d["N"]), int(d["N1"]), int(d["N2"]), int(d["TC"]), int(d["TR"])
+        r1, r2 = list(d.get("rad1", [])), list(d.get("rad2", []))
+        c.n_rad1, c.n_rad2 = len(r1), len(r2)
+        for i, r in enumerate(r1[:24]):
+            c.rad1[i] = int(r)
+        for i, r in enumerate(r2[:24]):
+            c.rad2[i] = int(r)
+        c.us, c.us_default = float(d.get("us", 0.0)), float(d.get("us_default", 0.0))
+        return c
 
 
 class KernelTime(ctypes.Structure):
@@ -113,6 +143,17 @@ def load():
     lib.fif_status_string.argtypes = [ctypes.c_int]
     lib.fif_plan_create.restype = ctypes.c_int
     lib.fif_plan_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(i64), i32, i32, ctypes.POINTER(_Options)]
+    lib.fif_plan_create_tuned.restype = ctypes.c_int
+    lib.fif_plan_create_tuned.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(i64), i32, i32, ctypes.POINTER(_Options),
+                                          ctypes.c_char_p]
+    lib.fif_plan_length_plan.restype = ctypes.c_int
+    lib.fif_plan_length_plan.argtypes = [vp, i64, ctypes.POINTER(LengthPlan)]
+    lib.fif_tune_cache_lookup.restype = ctypes.c_int
+    lib.fif_tune_cache_lookup.argtypes = [ctypes.c_char_p, ctypes.c_char_p, i64, ctypes.POINTER(LengthPlan)]
+    lib.fif_tune_cache_store.restype = ctypes.c_int
+    lib.fif_tune_cache_store.argtypes = [ctypes.c_char_p, ctypes.c_char_p, ctypes.POINTER(LengthPlan)]
+    lib.fif_device_tune_key.restype = ctypes.c_int
+    lib.fif_device_tune_key.argtypes = [ctypes.c_char_p, i32]
     lib.fif_plan_workspace_size.restype = ctypes.c_int
     lib.fif_plan_workspace_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
     lib.fif_plan_destroy.restype = ctypes.c_int

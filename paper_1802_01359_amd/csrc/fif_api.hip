@@ -19,6 +19,7 @@
 #include "fif_bigscan.hpp"
 #include "fif_model_internal.hpp"
 #include "fif_propose.hpp"
+#include "fif_tune.hpp"
 
 using namespace fif;
 
@@ -142,6 +143,8 @@ struct fif_plan {
     int64_t wshape_off = 0;
     size_t ws_taps = 0, ws_lam = 0, ws_wsum = 0;
     int32_t mt_shift = 0;           // test hook (FIF_DEBUG_MT_SHIFT): perturbs the deferred estimate
+    // lengths whose choice was measured (fif_plan_create_tuned): their times
+    std::map<int64_t, fif_length_plan> tuned;
     // learned proposal of m, and recording of the network inputs
     fif_model* model = nullptr;
     uint16_t* rec = nullptr;
@@ -169,6 +172,45 @@ struct fif_plan {
 };
 
 namespace {
+
+// Sizes of the structures host and kernels share, as the device compilation
+// saw them.  The host compares them with its own once before any launch: a
+// library whose host and device passes were compiled from different sources
+// would otherwise hand the kernels misplaced fields.  (Not const: a const
+// device array no kernel reads is left out of the device code, and the
+// runtime then cannot resolve the host's reference to it.)
+__device__ int64_t kDeviceAbi[5] = {(int64_t)sizeof(StepArgs), (int64_t)sizeof(ScanArgs),
+                                    (int64_t)sizeof(SigState), (int64_t)sizeof(LenPlan),
+                                    (int64_t)sizeof(SigDesc)};
+
+fif_status check_abi()
+{
+    static std::once_flag once;
+    static fif_status st = FIF_OK;
+    static std::string msg;
+    std::call_once(once, [] {
+        int64_t dev[5] = {0, 0, 0, 0, 0};
+        const hipError_t e = hipMemcpyFromSymbol(dev, HIP_SYMBOL(kDeviceAbi), sizeof(dev), 0, hipMemcpyDeviceToHost);
+        const int64_t host[5] = {(int64_t)sizeof(StepArgs), (int64_t)sizeof(ScanArgs), (int64_t)sizeof(SigState),
+                                 (int64_t)sizeof(LenPlan), (int64_t)sizeof(SigDesc)};
+        if (e != hipSuccess) {
+            st = FIF_ERR_DEVICE;
+            msg = std::string("reading the device structure sizes: ") + hipGetErrorString(e);
+        } else if (std::memcmp(dev, host, sizeof(dev)) != 0) {
+            st = FIF_ERR_DEVICE;
+            char buf[256];
+            std::snprintf(buf, sizeof(buf),
+                          "host and device structure sizes differ (%lld/%lld %lld/%lld %lld/%lld %lld/%lld "
+                          "%lld/%lld): the library was built from inconsistent sources",
+                          (long long)host[0], (long long)dev[0], (long long)host[1], (long long)dev[1],
+                          (long long)host[2], (long long)dev[2], (long long)host[3], (long long)dev[3],
+                          (long long)host[4], (long long)dev[4]);
+            msg = buf;
+        }
+    });
+    if (st != FIF_OK) return fail(st, "%s", msg.c_str());
+    return FIF_OK;
+}
 
 fif_status set_lds_limits()
 {
@@ -290,6 +332,63 @@ fif_status plan_length(int64_t N, LenPlan& lp)
     return FIF_OK;
 }
 
+// Length plan from an explicit choice (validated by choice_valid).
+fif_status plan_from_choice(const fif_length_plan& c, LenPlan& lp)
+{
+    if (!choice_valid(c)) return fail(FIF_ERR_INVALID_ARG, "invalid plan choice for length %lld", (long long)c.N);
+    std::memset(&lp, 0, sizeof(lp));
+    lp.N = c.N;
+    auto sub = [](int n, const int8_t* rad, int nr, SubFft& f) {
+        std::memset(&f, 0, sizeof(f));
+        f.n = n;
+        f.nrad = nr;
+        for (int i = 0; i < nr; ++i) f.rad[i] = rad[i];
+    };
+    if (c.N <= kFftCap) {
+        lp.two_pass = 0;
+        lp.N1 = 1;
+        lp.N2 = (int32_t)c.N;
+        lp.TC = lp.TR = 1;
+        sub((int)c.N, c.rad1, c.n_rad1, lp.f1);
+        return FIF_OK;
+    }
+    lp.two_pass = 1;
+    lp.N1 = c.N1;
+    lp.N2 = c.N2;
+    lp.TC = c.TC;
+    lp.TR = c.TR;
+    sub(c.N2, c.rad1, c.n_rad1, lp.f1);
+    sub(c.N1, c.rad2, c.n_rad2, lp.f2);
+    lp.paired = (lp.N1 % 2 == 0 && lp.N2 % 2 == 0 && lp.TC % 2 == 0) ? 1 : 0;
+    lp.spec_perm = lp.paired;
+    int64_t split = 1;
+    int shift = 0;
+    while (split * split < c.N) {
+        split *= 2;
+        ++shift;
+    }
+    lp.big_split = (int32_t)split;
+    lp.big_shift = shift;
+    return FIF_OK;
+}
+
+// The choice a length plan embodies.
+fif_length_plan choice_of(const LenPlan& lp)
+{
+    fif_length_plan c;
+    std::memset(&c, 0, sizeof(c));
+    c.N = lp.N;
+    c.N1 = lp.two_pass ? lp.N1 : 1;
+    c.N2 = lp.two_pass ? lp.N2 : (int32_t)lp.N;
+    c.TC = lp.two_pass ? lp.TC : 1;
+    c.TR = lp.two_pass ? lp.TR : 1;
+    c.n_rad1 = lp.f1.nrad;
+    for (int i = 0; i < lp.f1.nrad; ++i) c.rad1[i] = lp.f1.rad[i];
+    c.n_rad2 = lp.two_pass ? lp.f2.nrad : 0;
+    for (int i = 0; i < c.n_rad2; ++i) c.rad2[i] = lp.f2.rad[i];
+    return c;
+}
+
 template <typename T>
 T* upload(char* dbase, size_t off, const std::vector<T>& v, std::vector<char>& host)
 {
@@ -328,12 +427,20 @@ const char* fif_status_string(fif_status s)
     case FIF_ERR_DEVICE: return "device error";
     case FIF_ERR_NONFINITE: return "non-finite input";
     case FIF_ERR_CAPACITY: return "capacity exceeded";
+    case FIF_ERR_NOT_FOUND: return "not found";
     }
     return "unknown status";
 }
 
-fif_status fif_plan_create(fif_plan** out, const int64_t* lengths, int32_t B, int32_t max_imfs,
-                           const fif_options* opt_in)
+}  // extern "C"
+
+namespace {
+
+using ChoiceMap = std::map<int64_t, fif_length_plan>;
+
+// fif_plan_create, with the choices in `forced` for the lengths it lists.
+fif_status create_plan(fif_plan** out, const int64_t* lengths, int32_t B, int32_t max_imfs, const fif_options* opt_in,
+                       const ChoiceMap* forced)
 {
     g_err.clear();
     if (!out) return fail(FIF_ERR_INVALID_ARG, "plan pointer is null");
@@ -361,12 +468,12 @@ fif_status fif_plan_create(fif_plan** out, const int64_t* lengths, int32_t B, in
         if (!smooth7(N))
             return fail(FIF_ERR_UNSUPPORTED_LENGTH, "signal %d: length %lld has a prime factor > 7", b,
                         (long long)N);
-        if (opt.stop_mode != 0 && N / 2 > (int64_t)kScanBinsPerThread * kScanThreads)
-            return fail(FIF_ERR_INVALID_ARG, "signal %d: stop_mode %d supports lengths up to %d", b, opt.stop_mode,
-                        2 * kScanBinsPerThread * kScanThreads);
         if (!len_id.count(N)) {
             LenPlan lp;
-            st = plan_length(N, lp);
+            if (forced && forced->count(N))
+                st = plan_from_choice(forced->at(N), lp);
+            else
+                st = plan_length(N, lp);
             if (st) return st;
             len_id[N] = (int32_t)p->lens.size();
             p->lens.push_back(lp);
@@ -374,6 +481,8 @@ fif_status fif_plan_create(fif_plan** out, const int64_t* lengths, int32_t B, in
     }
 
     // all host-side validation is done: from here on the device is used
+    st = check_abi();
+    if (st) return st;
     st = set_lds_limits();
     if (st) return st;
     HIP_TRY(hipGetDevice(&p->device));
@@ -642,6 +751,16 @@ fif_status fif_plan_create(fif_plan** out, const int64_t* lengths, int32_t B, in
     HIP_TRY(hipDeviceSynchronize());
     *out = p.release();
     return FIF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fif_status fif_plan_create(fif_plan** out, const int64_t* lengths, int32_t B, int32_t max_imfs,
+                           const fif_options* opt_in)
+{
+    return create_plan(out, lengths, B, max_imfs, opt_in, nullptr);
 }
 
 fif_status fif_plan_workspace_size(const fif_plan* plan, size_t* bytes)
@@ -1052,6 +1171,132 @@ fif_status batched(fif_plan* p, const T* x, double delta, T* imfs, T* rem, int32
     return FIF_OK;
 }
 
+// ------------------------------------------------------------- autotuner
+
+// Synthetic input of the timing runs: three tones per signal plus a small
+// deterministic perturbation (any input with several IMFs will do).
+__global__ void k_tune_signal(float* __restrict__ x, int64_t total, int64_t N)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const int64_t n = i % N;
+    const double u = (double)n / (double)N;
+    const uint32_t h = (uint32_t)(i * 2654435761u);
+    x[i] = (float)(sinpi(2.0 * 3.0 * u) + 0.5 * sinpi(2.0 * (double)(N / 64) * u) +
+                   0.25 * sinpi(2.0 * (double)(N / 7) * u) + 1e-3 * ((double)(h >> 8) / 16777216.0 - 0.5));
+}
+
+// Largest divisor of n that is at most cap (>= 1).
+int64_t divisor_at_most(int64_t n, int64_t cap) { return largest_divisor_at_most(n, std::max<int64_t>(1, cap)); }
+
+// Candidate choices for a two-pass length: the three most balanced splits,
+// the widest pass-1 / pass-2 tiles and half of each, the built-in radix order
+// and its reverse.  The built-in choice comes first.
+std::vector<fif_length_plan> tune_candidates(int64_t N)
+{
+    std::vector<fif_length_plan> out;
+    LenPlan lp0;
+    if (plan_length(N, lp0) != FIF_OK || !lp0.two_pass) return out;
+    out.push_back(choice_of(lp0));
+    std::vector<std::pair<int64_t, int64_t>> splits;   // (N1, N2)
+    for (int64_t n2 = 2; n2 <= kTileCap; ++n2) {
+        if (N % n2) continue;
+        const int64_t n1 = N / n2;
+        if (n1 < 2 || n1 > kTileCap) continue;
+        splits.push_back({n1, n2});
+    }
+    std::sort(splits.begin(), splits.end(), [](const std::pair<int64_t, int64_t>& a, const std::pair<int64_t, int64_t>& b) {
+        const int64_t ma = std::max(a.first, a.second), mb = std::max(b.first, b.second);
+        return ma != mb ? ma < mb : a.second > b.second;
+    });
+    if (splits.size() > 3) splits.resize(3);
+    for (const auto& sp : splits) {
+        const int64_t N1 = sp.first, N2 = sp.second;
+        SubFft f1, f2;
+        if (!make_subfft(N2, f1) || !make_subfft(N1, f2)) continue;
+        const int64_t tc0 = divisor_at_most(N1, kTileCap / N2), tr0 = divisor_at_most(N2, kTileCap / N1);
+        const int64_t tcs[2] = {tc0, divisor_at_most(N1, tc0 / 2)};
+        const int64_t trs[2] = {tr0, divisor_at_most(N2, tr0 / 2)};
+        for (int rev = 0; rev < 2; ++rev)
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b) {
+                    if ((a == 1 && tcs[1] == tcs[0]) || (b == 1 && trs[1] == trs[0])) continue;
+                    fif_length_plan c;
+                    std::memset(&c, 0, sizeof(c));
+                    c.N = N;
+                    c.N1 = (int32_t)N1;
+                    c.N2 = (int32_t)N2;
+                    c.TC = (int32_t)tcs[a];
+                    c.TR = (int32_t)trs[b];
+                    c.n_rad1 = f1.nrad;
+                    c.n_rad2 = f2.nrad;
+                    for (int i = 0; i < f1.nrad; ++i) c.rad1[i] = f1.rad[rev ? f1.nrad - 1 - i : i];
+                    for (int i = 0; i < f2.nrad; ++i) c.rad2[i] = f2.rad[rev ? f2.nrad - 1 - i : i];
+                    if (!choice_valid(c)) continue;
+                    bool dup = false;
+                    for (const auto& o : out)
+                        dup = dup || std::memcmp(&o, &c, sizeof(c)) == 0;
+                    if (!dup) out.push_back(c);
+                }
+    }
+    return out;
+}
+
+// Microseconds of one decomposition (two IMFs) of a synthetic batch of
+// length-N signals with choice c, best of three after one warm-up run;
+// negative if the plan cannot be built or run.
+double time_choice(const fif_length_plan& c, const fif_options& opt)
+{
+    const int64_t N = c.N;
+    const int32_t Bt = (int32_t)std::max<int64_t>(1, std::min<int64_t>(256, ((int64_t)1 << 23) / N));
+    const int32_t J = 2;
+    std::vector<int64_t> lengths((size_t)Bt, N);
+    ChoiceMap forced{{N, c}};
+    fif_plan* tp = nullptr;
+    if (create_plan(&tp, lengths.data(), Bt, J, &opt, &forced) != FIF_OK) return -1.0;
+    std::unique_ptr<fif_plan> hold(tp);
+    const int64_t total = (int64_t)Bt * N;
+    const size_t bytes = tp->ws_total + sizeof(float) * (size_t)total * (J + 2) + 1024;
+    void* mem = nullptr;
+    if (hipMalloc(&mem, bytes) != hipSuccess) return -1.0;
+    DevBuf buf;
+    buf.p = mem;
+    char* b = (char*)mem;
+    void* ws = b;
+    float* x = (float*)(b + align_up(tp->ws_total, 256));
+    float* imfs = x + total;
+    float* rem = imfs + total * J;
+    int32_t* nimf = (int32_t*)(rem + total);
+    k_tune_signal<<<(unsigned)((total + 255) / 256), 256>>>(x, total, N);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -1.0;
+    double best = -1.0;
+    for (int r = 0; r < 4; ++r) {
+        (void)hipEventRecord(e0, nullptr);
+        if (batched<float>(tp, x, 1e-3, imfs, rem, nimf, nullptr, nullptr, ws, nullptr) != FIF_OK) break;
+        (void)hipEventRecord(e1, nullptr);
+        if (hipEventSynchronize(e1) != hipSuccess) break;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (r > 0 && (best < 0.0 || 1e3 * ms < best)) best = 1e3 * ms;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return best;
+}
+
+std::string device_key()
+{
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    hipDeviceProp_t prop;
+    std::memset(&prop, 0, sizeof(prop));
+    (void)hipGetDeviceProperties(&prop, dev);
+    int rt = 0;
+    (void)hipRuntimeGetVersion(&rt);
+    return key_text(prop.gcnArchName) + "/hip" + std::to_string(rt);
+}
+
 // ------------------------------------------- entry point without allocation
 
 // Workspace of fif_decompose_batched_static: a fixed array in the library's
@@ -1295,6 +1540,101 @@ fif_status fif_decompose_f64(const double* signal, int64_t N, fif_window window,
                              const fif_options* opt, void* stream)
 {
     return single<double>(signal, N, window, delta, max_imfs, imfs, remainder, n_imfs, info, opt, stream);
+}
+
+fif_status fif_plan_create_tuned(fif_plan** out, const int64_t* lengths, int32_t B, int32_t max_imfs,
+                                 const fif_options* opt_in, const char* tune_cache)
+{
+    g_err.clear();
+    if (!out) return fail(FIF_ERR_INVALID_ARG, "plan pointer is null");
+    *out = nullptr;
+    if (!lengths || B < 1) return fail(FIF_ERR_INVALID_ARG, "need at least one signal length");
+    fif_options opt;
+    fif_options_default(&opt);
+    if (opt_in) opt = *opt_in;
+    fif_status st = validate_opts(opt);
+    if (st) return st;
+    const char* path = tune_cache ? tune_cache : getenv("FIF_TUNE_CACHE");
+    const std::string key = device_key();
+    ChoiceMap chosen;
+    for (int32_t b = 0; b < B; ++b) {
+        const int64_t N = lengths[b];
+        if (N <= kFftCap || chosen.count(N) || !smooth7(N)) continue;
+        fif_length_plan c;
+        if (path && cache_lookup(path, key.c_str(), N, &c) == FIF_OK) {
+            chosen[N] = c;
+            continue;
+        }
+        const std::vector<fif_length_plan> cands = tune_candidates(N);
+        if (cands.empty()) continue;      // create_plan reports the length
+        int best = -1;
+        double best_us = 0.0, us0 = 0.0;
+        for (size_t i = 0; i < cands.size(); ++i) {
+            const double us = time_choice(cands[i], opt);
+            if (i == 0) us0 = us;
+            if (us > 0.0 && (best < 0 || us < best_us)) {
+                best = (int)i;
+                best_us = us;
+            }
+        }
+        if (best < 0) continue;           // nothing ran: the built-in choice
+        c = cands[(size_t)best];
+        // times at the cache file's resolution (ns), so that a plan made from
+        // the file reports what a freshly tuned one does
+        c.us = std::round(best_us * 1e3) / 1e3;
+        c.us_default = us0 > 0.0 ? std::round(us0 * 1e3) / 1e3 : 0.0;
+        chosen[N] = c;
+        if (path) (void)cache_store(path, key.c_str(), c);
+    }
+    g_err.clear();
+    fif_plan* p = nullptr;
+    st = create_plan(&p, lengths, B, max_imfs, &opt, &chosen);
+    if (st) return st;
+    p->tuned = chosen;
+    *out = p;
+    return FIF_OK;
+}
+
+fif_status fif_plan_length_plan(const fif_plan* plan, int64_t N, fif_length_plan* out)
+{
+    if (!plan || !out) return fail(FIF_ERR_INVALID_ARG, "null argument");
+    for (const auto& lp : plan->lens) {
+        if (lp.N != N) continue;
+        *out = choice_of(lp);
+        auto it = plan->tuned.find(N);
+        if (it != plan->tuned.end()) {
+            out->us = it->second.us;
+            out->us_default = it->second.us_default;
+        }
+        return FIF_OK;
+    }
+    return fail(FIF_ERR_NOT_FOUND, "the plan has no signal of length %lld", (long long)N);
+}
+
+fif_status fif_tune_cache_lookup(const char* path, const char* device_key_in, int64_t N, fif_length_plan* out)
+{
+    g_err.clear();
+    const fif_status st = cache_lookup(path, device_key_in, N, out);
+    if (st == FIF_ERR_INVALID_ARG) return fail(st, "null argument");
+    return st;
+}
+
+fif_status fif_tune_cache_store(const char* path, const char* device_key_in, const fif_length_plan* c)
+{
+    g_err.clear();
+    if (!c) return fail(FIF_ERR_INVALID_ARG, "null choice");
+    const fif_status st = cache_store(path, device_key_in, *c);
+    if (st != FIF_OK) return fail(st, "invalid choice or unwritable cache file");
+    return FIF_OK;
+}
+
+fif_status fif_device_tune_key(char* key, int32_t cap)
+{
+    if (!key || cap < 1) return fail(FIF_ERR_INVALID_ARG, "null or empty key buffer");
+    const std::string k = device_key();
+    std::strncpy(key, k.c_str(), (size_t)cap - 1);
+    key[cap - 1] = 0;
+    return FIF_OK;
 }
 
 fif_status fif_plan_set_proposal(fif_plan* plan, fif_model* model)

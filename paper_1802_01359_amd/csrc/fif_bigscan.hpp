@@ -19,6 +19,12 @@
 //                  yet.
 // Signals already decided skip the remaining launches.  Partial sums cross
 // workgroups only through kernel boundaries (no device-scope fences).
+//
+// Stop mode 1 (absolute criterion) searches the count c = m + 1, whose
+// numerator sum P lambda^2 mu^(c-1) is ||s_{m+1} - s_m||^2 times N pscale,
+// for the smallest c >= 2 below delta^2 N pscale; Theorem 5's N0 (from the
+// tiles' largest |R_j|^2) bounds it from above.  Stop mode 2 takes m = N0
+// and spends one FP64 round on the reported step norms.
 #pragma once
 #include "fif_kernels.hpp"
 
@@ -27,15 +33,17 @@ namespace fif {
 // geometric probes 1, 2, 4, 8, ...
 __device__ __forceinline__ int64_t geo_next(int64_t m) { return m * 2; }
 
-// Evenly spaced candidates strictly inside (lo, hi), at most kBigRefine: the
-// exponentials per bin grow with the candidates per round while the rounds
-// fall only with their logarithm.
+// Candidates strictly inside (lo, hi) at a common spacing D = (hi - lo) div
+// (n + 1), at most kBigRefine of them: lo + D, lo + 2D, ..., lo + nD < hi.
+// The common spacing lets the tiles build mu^(m-1) of every candidate from
+// the previous one by one multiplication.
 __device__ __forceinline__ void fill_inside(BigScan* G, int64_t lo, int64_t hi)
 {
     const int64_t gap = hi - lo - 1;
     const int n = (int)min((int64_t)kBigRefine, gap);
-    for (int i = 0; i < n; ++i) G->cand[i] = lo + ((int64_t)(i + 1) * (hi - lo)) / (n + 1);
-    // strictly increasing and inside (lo, hi) because (hi - lo) >= n + 1
+    const int64_t D = (hi - lo) / (n + 1);
+    for (int i = 0; i < n; ++i) G->cand[i] = lo + (int64_t)(i + 1) * D;
+    // strictly increasing, and lo + nD <= lo + n (hi - lo) / (n + 1) < hi
     G->ncand = n;
 }
 
@@ -81,15 +89,17 @@ __global__ __launch_bounds__(T) void k_bscan_prep(ScanArgs A)
             G->qthr = 0.0;
             G->n32 = G->n64 = 0;
             G->flags = 0;
-            G->lo = 0;
             G->hi = -1;
             G->elo = 0;
             G->ehi = -1;
             G->sd_lo = INFINITY;
             G->sd_hi = 0.0;
-            const int64_t cap = A.max_inner;
+            // counts searched: m (stop modes 0, 2) or c = m + 1 (stop mode 1)
+            const int64_t first = A.stop_mode == 1 ? 2 : 1;
+            const int64_t cap = A.max_inner + first - 1;
+            G->lo = first - 1;
             int n = 0;
-            for (int64_t m = 1; m < cap && n < kBigCand - 1; m = geo_next(m)) G->cand[n++] = m;
+            for (int64_t m = first; m < cap && n < kBigCand - 1; m = geo_next(m)) G->cand[n++] = m;
             G->cand[n++] = cap;
             G->ncand = n;
         }
@@ -155,9 +165,38 @@ __device__ __forceinline__ void bscan_tile_sums(const ScanArgs& A, const SigDesc
         const float* tau = A.gscr + d.gs_off;
         const float* av = tau + nh;
         const float* bv = av + nh;
-        float e[kBigCand];
-#pragma unroll
-        for (int i = 0; i < kBigCand; ++i) e[i] = (i < nc) ? (float)(G->cand[i] - 1) : 0.f;
+        // x_i = mu^(e_i), e_i = cand_i - 1.  When the round's counts follow
+        // one pattern -- even spacing (refinement) or doubling spacing
+        // (geometric probes, gallops), the last count possibly off the
+        // pattern (the cap) -- x_i = x_(i-1) r_i with r_1 = mu^(e_1 - e_0) and
+        // r_(i+1) = r_i (even) or r_i^2 (doubling): three exp2 per bin instead
+        // of one per candidate.  Other rounds (a proposal's seeds) take one
+        // exp2 per candidate.  The FP32 values only bracket m; the FP64 phase
+        // decides.  (The pattern is read from the uniform candidate list.)
+        int pat = 0;               // 0 generic, 1 even, 2 doubling
+        bool fresh_last = false;   // the last count is formed directly
+        if (nc >= 2) {
+            const int64_t d1 = G->cand[1] - G->cand[0];
+            for (int drop = 0; drop < 2 && pat == 0; ++drop) {
+                const int n = nc - drop;      // counts that must follow the pattern
+                bool even = true, dbl = true;
+                int64_t dp = d1;
+                for (int i = 2; i < n; ++i) {
+                    const int64_t di = G->cand[i] - G->cand[i - 1];
+                    even = even && di == d1;
+                    dbl = dbl && di == 2 * dp;
+                    dp = di;
+                }
+                if (n >= 2 && (even || dbl)) {
+                    pat = even ? 1 : 2;
+                    fresh_last = drop == 1;
+                }
+            }
+        }
+        const float e0 = (float)(G->cand[0] - 1);
+        const float d1f = nc >= 2 ? (float)(G->cand[1] - G->cand[0]) : 0.f;
+        const float elast = (float)(G->cand[nc - 1] - 1);
+        const bool dbl = pat == 2;
         float acc[2 * kBigCand];
 #pragma unroll
         for (int i = 0; i < 2 * kBigCand; ++i) acc[i] = 0.f;
@@ -176,15 +215,38 @@ __device__ __forceinline__ void bscan_tile_sums(const ScanArgs& A, const SigDesc
                 bq[q] = bv[j - 1];
             }
         }
+        if (pat == 0) {
 #pragma unroll
-        for (int q = 0; q < BPT; ++q) {
-            const float tj = tq[q], aj = aq[q], bj = bq[q];
+            for (int q = 0; q < BPT; ++q) {
+                const float tj = tq[q], aj = aq[q], bj = bq[q];
 #pragma unroll
-            for (int i = 0; i < kBigCand; ++i) {
-                if (i < nc) {
-                    const float x = (e[i] == 0.f) ? 1.f : __builtin_amdgcn_exp2f(e[i] * tj);
-                    acc[2 * i] += aj * x;
-                    acc[2 * i + 1] += bj * x;
+                for (int i = 0; i < kBigCand; ++i) {
+                    if (i < nc) {
+                        const float ei = (float)(G->cand[i] - 1);
+                        const float x = (ei == 0.f) ? 1.f : __builtin_amdgcn_exp2f(ei * tj);
+                        acc[2 * i] += aj * x;
+                        acc[2 * i + 1] += bj * x;
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < BPT; ++q) {
+                const float tj = tq[q], aj = aq[q], bj = bq[q];
+                float x = (e0 == 0.f) ? 1.f : __builtin_amdgcn_exp2f(e0 * tj);
+                float r = __builtin_amdgcn_exp2f(d1f * tj);
+                const float xl = __builtin_amdgcn_exp2f(elast * tj);
+#pragma unroll
+                for (int i = 0; i < kBigCand; ++i) {
+                    if (i < nc) {
+                        if (i > 0) {
+                            x *= r;
+                            r = dbl ? r * r : r;
+                        }
+                        const float xi = (fresh_last && i == nc - 1) ? xl : x;
+                        acc[2 * i] += aj * xi;
+                        acc[2 * i + 1] += bj * xi;
+                    }
                 }
             }
         }
@@ -362,13 +424,19 @@ __device__ __forceinline__ void bscan_decide(const ScanArgs& A, const SigDesc& d
     const double* Asum = tot;          // numerator of candidate i at Asum[2i]
     const double* Bsum = tot + 1;      // denominator at Bsum[2i]
     const double delta = A.delta;
-    const int64_t cap = A.max_inner;
+    const int mode = A.stop_mode;
+    // stop mode 1 counts c = m + 1 (c = 1, m = 0, is never an answer)
+    const int64_t first = mode == 1 ? 2 : 1;
+    const int64_t cap = A.max_inner + first - 1;
+    // ||s_{m+1} - s_m||^2 N pscale below this passes the absolute test
+    const double thr_abs = delta * delta * (double)d.N * G->pscale;
     if (G->phase < 2) {
         G->n32 += 1;
         const double d2 = (double)(float)(delta * delta);
         int q = -1;
         for (int i = 0; i < nc; ++i) {
-            const bool ok = Bsum[2 * i] <= 0.0 || Asum[2 * i] <= d2 * Bsum[2 * i];
+            const bool ok = mode == 1 ? Asum[2 * i] < thr_abs
+                                      : (Bsum[2 * i] <= 0.0 || Asum[2 * i] <= d2 * Bsum[2 * i]);
             if (ok) {
                 q = i;
                 break;
@@ -381,6 +449,12 @@ __device__ __forceinline__ void bscan_decide(const ScanArgs& A, const SigDesc& d
         } else {
             lo = G->cand[nc - 1];
         }
+        if (mode == 1 && G->mt > 0 && (hi < 0 || hi > G->mt)) {
+            // Theorem 5: c = N0 + 1 passes the absolute test (G->mt holds it
+            // after the first round); the FP64 phase checks the bracket
+            hi = G->mt;
+        }
+        if (lo >= hi && hi >= 0) lo = hi - 1;
         int64_t mt = -1;
         if (q < 0 && lo >= cap)
             mt = cap;
@@ -392,7 +466,7 @@ __device__ __forceinline__ void bscan_decide(const ScanArgs& A, const SigDesc& d
             // FP64 confirmation of SD_mt <= delta < SD_{mt-1}
             G->phase = 2;
             G->mt = mt;
-            if (mt == 1) {
+            if (mt == first) {
                 G->cand[0] = 1;
                 G->ncand = 1;
             } else {
@@ -411,12 +485,23 @@ __device__ __forceinline__ void bscan_decide(const ScanArgs& A, const SigDesc& d
     }
     // FP64 phase: tot holds the logarithms of the sums (-inf: empty)
     G->n64 += 1;
+    if (mode == 2) {
+        // the a-priori count needs no search: report the step norms at m
+        // (c = m + 1) and m - 1 (c = m), computed by this round
+        G->m = G->mt;
+        G->sd_m = sqrt(exp(Asum[2]) / ((double)d.N * G->pscale));   // c = m + 1
+        G->sd_p = sqrt(exp(Asum[0]) / ((double)d.N * G->pscale));   // c = m
+        G->phase = 3;
+        return;
+    }
     int64_t elo = G->elo, ehi = G->ehi;
     double sd_lo = G->sd_lo, sd_hi = G->sd_hi;
     for (int i = 0; i < nc; ++i) {
-        const double sd = Bsum[2 * i] > -INFINITY ? exp(0.5 * (Asum[2 * i] - Bsum[2 * i])) : 0.0;
+        const double sd = mode == 1 ? sqrt(exp(Asum[2 * i]) / ((double)d.N * G->pscale))
+                                    : (Bsum[2 * i] > -INFINITY ? exp(0.5 * (Asum[2 * i] - Bsum[2 * i])) : 0.0);
         const int64_t c = G->cand[i];
-        if (sd <= delta) {
+        const bool ok = (mode == 1 ? sd < delta : sd <= delta) && c >= first;
+        if (ok) {
             if (ehi < 0 || c < ehi) {
                 ehi = c;
                 sd_hi = sd;
@@ -432,12 +517,12 @@ __device__ __forceinline__ void bscan_decide(const ScanArgs& A, const SigDesc& d
     G->sd_lo = sd_lo;
     G->sd_hi = sd_hi;
     if (ehi >= 0 && ehi - elo <= 1) {
-        G->m = ehi;
+        G->m = ehi - (first - 1);
         G->sd_m = sd_hi;
-        G->sd_p = (ehi == 1) ? INFINITY : sd_lo;
+        G->sd_p = (mode == 0 && ehi == 1) ? INFINITY : sd_lo;
         G->phase = 3;
     } else if (ehi < 0 && elo >= cap) {
-        G->m = cap;
+        G->m = cap - (first - 1);
         G->sd_m = sd_lo;
         G->sd_p = sd_lo;
         G->flags |= FIF_IMF_CAP;
@@ -526,13 +611,34 @@ __global__ __launch_bounds__(64 * kDecideGroups) void k_bscan_decide(ScanArgs A)
     bscan_tile_totals(A, d, G->ncand, G->phase >= 2, part, partm, tot);
     __syncthreads();
     if (threadIdx.x == 0) {
+        bool skip = false;       // stop mode 2: this round only found N0
         if (G->phase < 2 && G->n32 == 0) {
-            // after the sweep: the noise floor from the tiles' largest |R_j|^2
+            // after the sweep: the tiles' largest |R_j|^2 give the noise floor
+            // of the relative test, or Theorem 5's N0 (with the DC bin)
             double q = 0.0;
             for (int t = 0; t < d.n_btiles; ++t) q = fmax(q, A.bqmax[d.bt_off + t]);
-            G->qthr = kSdNoise * q;
+            G->qthr = A.stop_mode == 0 ? kSdNoise * q : 0.0;
+            G->mt = 0;
+            if (A.stop_mode != 0) {
+                const double2 r0 = (((A.t & 1) ? A.spec1 : A.spec0) + d.spec_off)[0];
+                const int64_t n0 = apriori_n0(fmax(q, r0.x * r0.x + r0.y * r0.y), G->L, d.N, A.delta);
+                if (A.stop_mode == 1) {
+                    G->mt = min(n0, A.max_inner) + 1;     // as a count c = m + 1
+                } else {
+                    // m = N0 (capped): one FP64 round for the norms at m, m - 1
+                    const int64_t m = min(n0, A.max_inner);
+                    if (n0 > A.max_inner) G->flags |= FIF_IMF_CAP;
+                    G->n32 = 0;            // no search: the sweep only found N0
+                    G->phase = 2;
+                    G->mt = m;
+                    G->cand[0] = m;        // c = m: ||s_m - s_{m-1}||
+                    G->cand[1] = m + 1;    // c = m + 1: ||s_{m+1} - s_m||
+                    G->ncand = 2;
+                    skip = true;
+                }
+            }
         }
-        bscan_decide(A, d, G, tot);
+        if (!skip) bscan_decide(A, d, G, tot);
     }
 }
 

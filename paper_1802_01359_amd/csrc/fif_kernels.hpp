@@ -218,6 +218,8 @@ __device__ __forceinline__ double dval(long long k)
     return __longlong_as_double(k >= 0 ? k : (k ^ 0x7fffffffffffffffLL));
 }
 
+
+
 // ------------------------------------------------------------ reductions --
 
 // Butterfly sum within each half wave; equal bits in every lane of a half
@@ -341,6 +343,21 @@ __device__ __forceinline__ double lambda_at(int64_t j, const Lam& w)
     const double q = w.sinT[t] * w.isinT[j] * w.invL;
     const double q2 = q * q;
     return q2 * q2;
+}
+
+// lambda_j in FP32 for the FP32 search for m (the FP64 lambda_at decides
+// everywhere else): the reduced argument t = L j mod N is exact as before,
+// sin(pi t / N) comes from sinpif instead of a table gather (a random access
+// per bin), 1 / sin(pi j / N) from the table (read in bin order).
+__device__ __forceinline__ float lambda_f32(int64_t j, const Lam& w, float invNf, float invLf)
+{
+    if (j == 0) return 1.f;
+    if (w.tab) return (float)w.tab[j];
+    int64_t t = w.mask ? ((w.Lmod * j) & w.mask) : mulmod53(w.Lmod, j, w.N, w.invN);
+    if (t > w.N - t) t = w.N - t;
+    const float q = sinpif((float)t * invNf) * (float)w.isinT[j] * invLf;
+    const float q2 = q * q;
+    return fminf(q2 * q2, 1.f);
 }
 
 // x^e by binary powering (e >= 0)
@@ -1268,6 +1285,38 @@ __global__ __launch_bounds__(T) void k_scan_prologue(ScanArgs A)
     if (threadIdx.x == 0 && sh_i[0] >= 0) S->L = sh_i[0];
 }
 
+// Theorem 5: the smallest N0 >= 1 with N0^N0 / (N0+1)^(N0+1) <
+// delta / (||U^T r||_inf sqrt(N - 1 - k)), U the unitary DFT (||U^T r||_inf =
+// max_j |R_j| / sqrt(N), mzb = max_j |R_j|^2 over every bin), k = gcd(L, N) - 1
+// the number of exact zero eigenvalues; compared in logarithms.  For every
+// m >= N0, ||s_{m+1} - s_m|| < delta (inequality "N0_discrete").
+__device__ __forceinline__ int64_t apriori_n0(double mzb, int64_t L, int64_t N, double delta)
+{
+    int64_t ga = L, gb = N;
+    while (gb) {
+        const int64_t r = ga % gb;
+        ga = gb;
+        gb = r;
+    }
+    const int64_t rest = N - 1 - (ga - 1);
+    const double st_inf = sqrt(mzb / (double)N);
+    if (!(st_inf > 0.0) || rest <= 0) return 1;
+    const double rhs = log(delta / (st_inf * sqrt((double)rest)));
+    auto lhs = [](int64_t n) { return (double)n * log((double)n) - (double)(n + 1) * log((double)(n + 1)); };
+    int64_t hi2 = 1;
+    while (lhs(hi2) >= rhs && hi2 < ((int64_t)1 << 50)) hi2 *= 2;
+    int64_t lo2 = hi2 / 2;
+    if (lo2 == 0) return 1;
+    while (hi2 - lo2 > 1) {
+        const int64_t mid = (lo2 + hi2) / 2;
+        if (lhs(mid) < rhs)
+            hi2 = mid;
+        else
+            lo2 = mid;
+    }
+    return hi2;
+}
+
 // Probes of the bracketing phase: m = 1, 2, 4, 16, ..., 4^10.
 constexpr int kGeo = 12;
 __device__ __forceinline__ int64_t geo_m(int q) { return q == 0 ? 1 : q == 1 ? 2 : ((int64_t)1 << (2 * (q - 1))); }
@@ -1322,7 +1371,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
     const double inv_np = 1.0 / ((double)N * pscale);
     const float lnthr_abs = (float)log(delta * delta * (double)N * pscale);
     auto ok = [&](double sd) { return SMODE != 0 ? sd < delta : sd <= delta; };
-    double mz = 0.0;          // largest |R_j|^2, j >= 1 (stop modes 0 and 2)
+    double mz = 0.0;          // largest |R_j|^2, j >= 1
 
     // ---- first sweep: FP32 copies of the weighted power b, power*lambda^2
     //      a, and tau = log2 mu, mu = (1 - lambda)^2 (DC kept aside since
@@ -1331,13 +1380,13 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
     extern __shared__ float lds_a[];
     const SpecMap smap = make_specmap(lp);
     auto weight = [&](int j) -> double { return (2 * (int64_t)j == N) ? 1.0 : 2.0; };
-    // v: spectrum of bin jb
+    // v: spectrum of bin jb; lambda in FP32 (this search only brackets m)
+    const float invNf = 1.f / (float)N, invLf = 1.f / (float)L;
     auto sweep_bin = [&](double2 v, int64_t jb, float& tau, float& av, float& bv) {
         const double P = weight(jb) * (v.x * v.x + v.y * v.y) * pscale;
-        const double lam = lambda_at(jb, lw);
-        const float lf = (float)lam;
+        const float lf = lambda_f32(jb, lw, invNf, invLf);
         bv = (float)P;
-        av = (float)(P * lam * lam);
+        av = bv * lf * lf;
         tau = 2.8853900817779268f * log1pf(-lf);  // 2 log2(1 - lambda)
     };
     // bins in groups of SG: the group's loads are issued together (memory
@@ -1369,7 +1418,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
             if (j <= nh) {
                 sweep_bin(v[g], jb[g], tau_r[i], av, b_r[i]);
                 // after the group's loads were issued, not between them
-                if (SMODE != 1) mz = fmax(mz, v[g].x * v[g].x + v[g].y * v[g].y);
+                mz = fmax(mz, v[g].x * v[g].x + v[g].y * v[g].y);
             }
             lds_a[i * T + tid] = av;
         }
@@ -1417,39 +1466,9 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
     int64_t mt;
     uint32_t flags = 0;
     if (SMODE == 2) {
-        // Theorem 5: smallest N0 >= 1 with N0^N0 / (N0+1)^(N0+1) <
-        // delta / (||U^T r||_inf sqrt(N - 1 - k)), k = gcd(L, N) - 1 zero
-        // eigenvalues, compared in logarithms (every thread alike)
         double mn_unused = INFINITY, mzb = fmax(mz, P0 / pscale);
         block_minmax<T>(mn_unused, mzb, shd);
-        int64_t ga = L, gb = N;
-        while (gb) {
-            const int64_t r = ga % gb;
-            ga = gb;
-            gb = r;
-        }
-        const int64_t rest = N - 1 - (ga - 1);
-        const double st_inf = sqrt(mzb / (double)N);
-        int64_t n0 = 1;
-        if (st_inf > 0.0 && rest > 0) {
-            const double rhs = log(delta / (st_inf * sqrt((double)rest)));
-            auto lhs = [](int64_t n) { return (double)n * log((double)n) - (double)(n + 1) * log((double)(n + 1)); };
-            int64_t hi2 = 1;
-            while (lhs(hi2) >= rhs && hi2 < ((int64_t)1 << 50)) hi2 *= 2;
-            int64_t lo2 = hi2 / 2;
-            if (lo2 == 0) {
-                n0 = 1;
-            } else {
-                while (hi2 - lo2 > 1) {
-                    const int64_t mid = (lo2 + hi2) / 2;
-                    if (lhs(mid) < rhs)
-                        hi2 = mid;
-                    else
-                        lo2 = mid;
-                }
-                n0 = hi2;
-            }
-        }
+        const int64_t n0 = apriori_n0(mzb, L, N, delta);
         mt = n0;
         if (mt > cap) {
             mt = cap;
@@ -1459,6 +1478,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
         int64_t lo = 0, hi = -1;
         float flo = INFINITY, fhi = 0.f;
         const int64_t mp = A.prop ? A.prop[s] : 0;
+        int64_t top = cap;        // largest count the FP32 search considers
         if (mp > 0) {
             // bracket from the proposal: probe it, then walk away from it
             // in steps growing fourfold from mp/16 until f changes sign
@@ -1497,9 +1517,16 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
                 }
             }
         } else {
+            // stop mode 1: Theorem 5's N0 satisfies the absolute test, so
+            // the search needs no probe above it (Section 4 scans up to N0)
+            if (SMODE == 1) {
+                double mn_unused = INFINITY, mzb = fmax(mz, P0 / pscale);
+                block_minmax<T>(mn_unused, mzb, shd);
+                top = min(cap, apriori_n0(mzb, L, N, delta));
+            }
             for (int q = 0; q < kGeo; ++q) {
                 const int64_t mq = geo_m(q);
-                if (mq >= cap) break;
+                if (mq >= top) break;
                 const float fq = f32(mq);
                 if (fq <= 0.f) {
                     hi = mq;
@@ -1510,18 +1537,18 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
                 flo = fq;
             }
             if (hi < 0) {
-                // no probe below the cap satisfies the test
-                const float fc = f32(cap);
+                // no probe below the top satisfies the test
+                const float fc = f32(top);
                 if (fc <= 0.f) {
-                    hi = cap;
+                    hi = top;
                     fhi = fc;
                 } else {
-                    lo = cap;
+                    lo = top;
                 }
             }
         }
         if (hi < 0) {
-            mt = cap;
+            mt = top;
         } else {
             int side = 0;  // Illinois: endpoint kept twice in a row gets its f halved
             int64_t last_width = hi - lo;
@@ -1720,7 +1747,9 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
                 break;
             }
             if (stage == 0) {
-                const bool okp = ok(sp);
+                // m = 1 has no predecessor to reject it (stop mode 1 reports
+                // ||s_1 - s_0|| as sd_prev, which may be below delta too)
+                const bool okp = cand > 1 && ok(sp);
                 if (okm && !okp) {
                     m = cand;
                     sd_m = sm;

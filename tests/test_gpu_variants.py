@@ -13,7 +13,7 @@ import pytest
 
 import siggen
 from oracle import fif_spectral as fs
-from test_gpu_parity import _check, _signal
+from test_gpu_parity import _check, _signal  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -51,15 +51,36 @@ def _batch_vs_oracle(lengths, delta, max_imfs, dtype, oracle_kw, lam_abs=None, *
     return info, n
 
 
-@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-def test_absolute_stop(dtype):
-    info, n = _batch_vs_oracle(SMALL, 1e-2, 5, dtype, dict(stop="abs"), stop_mode=1)
+@pytest.mark.parametrize("dtype,lengths,imfs", [(torch.float64, SMALL, 5), (torch.float32, SMALL, 5),
+                                                (torch.float32, LARGE, 3)])
+def test_absolute_stop(dtype, lengths, imfs):
+    """LARGE: 131072 and 262144 samples take the multi-workgroup search, with
+    Theorem 5's N0 as its upper bracket."""
+    info, n = _batch_vs_oracle(lengths, 1e-2, imfs, dtype, dict(stop="abs"), stop_mode=1)
     assert np.all(info["m"][n > 0][:, 0] >= 1) if n.max() > 0 else True
 
 
+def test_absolute_stop_small_signal_takes_one_step():
+    """A residual whose first step ||s_1 - s_0|| is already below delta: the
+    smallest m >= 1 with ||s_{m+1} - s_m|| < delta is 1 (there is no m = 0),
+    on both sides."""
+    lengths = [4096, 1000, 8192, 65536]
+    sigs = [2e-5 * _signal(N, 700 + i) for i, N in enumerate(lengths)]
+    plan = fif.Plan(lengths, 3, fif.Options(stop_mode=1))
+    out = plan.run(torch.tensor(np.concatenate(sigs), dtype=torch.float64, device="cuda"), 1e-2)
+    torch.cuda.synchronize()
+    info = out.info()
+    n = out.n_imfs.cpu().numpy()
+    for b, N in enumerate(lengths):
+        ref = fs.decompose(sigs[b], 1e-2, 3, stop="abs")
+        assert ref.n_imfs >= 1 and ref.m[0] == 1 and ref.sd_prev[0] < 1e-2
+        _check(ref, sigs[b], out.imfs_of(b).cpu().numpy(), out.remainder_of(b).cpu().numpy(), info[b], int(n[b]),
+               1e-2, True)
+
+
 def test_apriori_n0():
-    info, n = _batch_vs_oracle([4096, 1000, 30, 8192, 65536], 1e-3, 3, torch.float64, dict(stop="apriori"),
-                               stop_mode=2)
+    info, n = _batch_vs_oracle([4096, 1000, 30, 8192, 65536, 131072, 262144], 1e-3, 3, torch.float64,
+                               dict(stop="apriori"), stop_mode=2)
     # no search: evals record one FP64 pass and no FP32 pass
     ev = info["evals"][np.arange(3)[None, :] < n[:, None]]
     assert np.all((ev & 0xffff) == 0) and np.all((ev >> 16) == 1)

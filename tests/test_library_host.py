@@ -78,8 +78,6 @@ def _plan_status(lib, lengths, max_imfs=4, **opt):
     ([4096], dict(gamma=-0.1), -1),
     ([4096], dict(mask_rule=2, peak_rho=0.0), -1),
     ([4096], dict(mask_rule=2, peak_rho=1.5), -1),
-    ([4096, 131072], dict(stop_mode=1), -1),   # stop modes 1, 2: lengths <= 65536
-    ([262144], dict(stop_mode=2), -1),
     ([4096], dict(window=[1.0]), -1),                 # fewer than two samples
     ([4096], dict(window=[0.0, 1.0]), -1),            # first sample not > 0
     ([4096], dict(window=[1.0, -0.5, 0.0]), -1),      # negative sample
