@@ -169,9 +169,10 @@ fif_status fif_plan_create(fif_plan** plan, const int64_t* lengths, int32_t B, i
  * How one signal length is transformed: one LDS pass (N <= 8192: N1 = 1,
  * N2 = N, TC = TR = 1), or the four-step split N = N1 * N2 whose pass 1
  * transforms TC columns of length N2 per workgroup and pass 2 TR rows of
- * length N1 (TC * N2 and TR * N1 at most 4096 elements), each length-n
- * transform a sequence of radix passes (2, 3, 4, 5, 7 or 8, first pass
- * first).  The FFT is what Section 4 makes the cost of each IMF; which
+ * length N1 (TC * N2 and TR * N1 at most 4096 elements; 8192 where a
+ * factor exceeds 2048, so that a tile still holds two columns or rows),
+ * each length-n transform a sequence of radix passes (2, 3, 4, 5, 7 or 8,
+ * first pass first).  The FFT is what Section 4 makes the cost of each IMF; which
  * split, tiles and radix order run fastest is a property of the device.
  */
 typedef struct {

@@ -124,6 +124,7 @@ struct fif_plan {
     hipGraphExec_t gexec = nullptr;
     std::vector<uintptr_t> gkey;
     size_t lds_single = 0, lds_p1 = 0, lds_p2 = 0;
+    bool wide = false;              // a length uses tiles above kTileCap elements
     // device copies (one allocation)
     DevBuf dmeta, dtabs;
     SigDesc* d_sigs = nullptr;
@@ -245,6 +246,22 @@ fif_status set_lds_limits()
         set((const void*)k_pass2<MODE_FORWARD, double, double>);
         set((const void*)k_pass2<MODE_STEP, double, double>);
         set((const void*)k_pass2<MODE_REMAINDER, double, double>);
+        set((const void*)k_pass1<MODE_WINDOW, double, false, kTileCapBig>);
+        set((const void*)k_pass2<MODE_WINDOW, double, double, kTileCapBig>);
+        set((const void*)k_pass1<MODE_FORWARD, float, false, kTileCapBig>);
+        set((const void*)k_pass1<MODE_STEP, float, false, kTileCapBig>);
+        set((const void*)k_pass1<MODE_STEP, float, true, kTileCapBig>);
+        set((const void*)k_pass1<MODE_REMAINDER, float, false, kTileCapBig>);
+        set((const void*)k_pass1<MODE_FORWARD, double, false, kTileCapBig>);
+        set((const void*)k_pass1<MODE_STEP, double, false, kTileCapBig>);
+        set((const void*)k_pass1<MODE_STEP, double, true, kTileCapBig>);
+        set((const void*)k_pass1<MODE_REMAINDER, double, false, kTileCapBig>);
+        set((const void*)k_pass2<MODE_FORWARD, float, float, kTileCapBig>);
+        set((const void*)k_pass2<MODE_STEP, float, float, kTileCapBig>);
+        set((const void*)k_pass2<MODE_REMAINDER, float, float, kTileCapBig>);
+        set((const void*)k_pass2<MODE_FORWARD, double, double, kTileCapBig>);
+        set((const void*)k_pass2<MODE_STEP, double, double, kTileCapBig>);
+        set((const void*)k_pass2<MODE_REMAINDER, double, double, kTileCapBig>);
         set((const void*)k_scan<kScanBinsPerThread, false, 0>);
         set((const void*)k_scan<kScanBinsPerThread, true, 0>);
         set((const void*)k_scan<kScanBinsPerThread, false, 1>);
@@ -318,6 +335,10 @@ fif_status plan_length(int64_t N, LenPlan& lp)
         return fail(FIF_ERR_UNSUPPORTED_LENGTH, "length %lld has a prime factor > 7", (long long)N);
     lp.TC = (int32_t)largest_divisor_at_most(lp.N1, kTileCap / lp.N2);
     lp.TR = (int32_t)largest_divisor_at_most(lp.N2, kTileCap / lp.N1);
+    // a single column (row) per tile reads the spectrum (writes the output)
+    // at a stride of N1 (N2) elements: take two per wide tile instead
+    if (lp.TC == 1 && lp.N1 % 2 == 0 && 2 * (int64_t)lp.N2 <= kTileCapBig) lp.TC = 2;
+    if (lp.TR == 1 && lp.N2 % 2 == 0 && 2 * (int64_t)lp.N1 <= kTileCapBig) lp.TR = 2;
     // mirror-paired column tiles need N1, N2 and the tile width even
     lp.paired = (lp.N1 % 2 == 0 && lp.N2 % 2 == 0 && lp.TC % 2 == 0) ? 1 : 0;
     lp.spec_perm = lp.paired;
@@ -528,6 +549,21 @@ fif_status create_plan(fif_plan** out, const int64_t* lengths, int32_t B, int32_
     }
     p->wshape_off = dcount;
     dcount += (int64_t)p->wshape.size();
+    {
+        // lambda_j's sines: tables while all of them fit the cache, else
+        // both evaluated in place (FIF_LAMBDA_SINES=table|sin|both overrides)
+        int64_t sin_bytes = 0;
+        for (const auto& lp : p->lens) sin_bytes += (int64_t)sizeof(double) * (lp.N / 2 + 1);
+        int inl = sin_bytes > kSinTableHotBytes ? 2 : 0;
+        if (const char* env = getenv("FIF_LAMBDA_SINES")) {
+            const std::string v(env);
+            inl = v == "table" ? 0 : v == "sin" ? 1 : v == "both" ? 2 : inl;
+        }
+        for (auto& lp : p->lens) {
+            lp.lam_inline = inl;
+            lp.lam_pad = 0;
+        }
+    }
 
     // signals, work lists, workspace sizes
     int64_t off = 0, spec = 0, inter = 0, inter_max = 0, gscr = 0, resid = 0;
@@ -583,6 +619,7 @@ fif_status create_plan(fif_plan** out, const int64_t* lengths, int32_t B, int32_
             for (int32_t t = 0; t < lp.N2 / lp.TR; ++t) p->w_p2.push_back({b, t});
             p->lds_p1 = std::max(p->lds_p1, (size_t)lp.TC * lp.N2 * sizeof(double2));
             p->lds_p2 = std::max(p->lds_p2, (size_t)lp.TR * lp.N1 * sizeof(double2));
+            if ((int64_t)lp.TC * lp.N2 > kTileCap || (int64_t)lp.TR * lp.N1 > kTileCap) p->wide = true;
         }
         if (d.bs < 0)
             p->scan_small.push_back(b);
@@ -888,6 +925,25 @@ Bound bind(const fif_plan* p, void* ws, double delta, fif_imf_info* info)
     return b;
 }
 
+// Four-step passes with the plan's tile size.
+template <int MODE, typename T, bool REDO = false>
+void run_pass1(const fif_plan* p, unsigned grid, hipStream_t s, const StepArgs& A, const T* x)
+{
+    if (p->wide)
+        k_pass1<MODE, T, REDO, kTileCapBig><<<grid, kFftThreads, p->lds_p1, s>>>(A, x);
+    else
+        k_pass1<MODE, T, REDO, kTileCap><<<grid, kFftThreads, p->lds_p1, s>>>(A, x);
+}
+template <int MODE, typename InT, typename OutT>
+void run_pass2(const fif_plan* p, unsigned grid, hipStream_t s, const StepArgs& A, const InT* x, OutT* imfs,
+               OutT* rem)
+{
+    if (p->wide)
+        k_pass2<MODE, InT, OutT, kTileCapBig><<<grid, kFftThreads, p->lds_p2, s>>>(A, x, imfs, rem);
+    else
+        k_pass2<MODE, InT, OutT, kTileCap><<<grid, kFftThreads, p->lds_p2, s>>>(A, x, imfs, rem);
+}
+
 template <typename T>
 void launch_init(const fif_plan* p, Bound& b, const T* x, hipStream_t s)
 {
@@ -911,11 +967,11 @@ void launch_init(const fif_plan* p, Bound& b, const T* x, hipStream_t s)
         A.work = p->d_p1;
         {
             Timed tm(p, "pass1_fwd", s);
-            k_pass1<MODE_FORWARD, T><<<(unsigned)p->w_p1.size(), kFftThreads, p->lds_p1, s>>>(A, x);
+            run_pass1<MODE_FORWARD, T>(p, (unsigned)p->w_p1.size(), s, A, x);
         }
         A.work = p->d_p2;
         Timed tm(p, "pass2_fwd", s);
-        k_pass2<MODE_FORWARD, T, T><<<(unsigned)p->w_p2.size(), kFftThreads, p->lds_p2, s>>>(A, x, nullptr, nullptr);
+        run_pass2<MODE_FORWARD, T, T>(p, (unsigned)p->w_p2.size(), s, A, x, (T*)nullptr, (T*)nullptr);
     }
 }
 
@@ -947,10 +1003,10 @@ void launch_window(const fif_plan* p, Bound& b, void* ws, hipStream_t s, const f
     }
     if (g.p1.count) {
         A.work = p->d_p1 + g.p1.begin;
-        k_pass1<MODE_WINDOW, double><<<(unsigned)g.p1.count, kFftThreads, p->lds_p1, s>>>(A, taps);
+        run_pass1<MODE_WINDOW, double>(p, (unsigned)g.p1.count, s, A, (const double*)taps);
         A.work = p->d_p2 + g.p2.begin;
-        k_pass2<MODE_WINDOW, double, double><<<(unsigned)g.p2.count, kFftThreads, p->lds_p2, s>>>(A, taps, nullptr,
-                                                                                                   nullptr);
+        run_pass2<MODE_WINDOW, double, double>(p, (unsigned)g.p2.count, s, A, (const double*)taps, (double*)nullptr,
+                                               (double*)nullptr);
     }
 }
 
@@ -1061,7 +1117,7 @@ void launch_step(const fif_plan* p, Bound& b, int t, const T* x, T* imfs, void* 
         A.work = p->d_p1 + g.p1.begin;
         {
             Timed tm(p, "pass1_step", s);
-            k_pass1<MODE_STEP, T><<<(unsigned)g.p1.count, kFftThreads, p->lds_p1, s>>>(A, x);
+            run_pass1<MODE_STEP, T>(p, (unsigned)g.p1.count, s, A, x);
         }
         if (b.sc.defer && g.ssmall.count) {
             // deferred FP64 check of m, then the rare redo: exact search and
@@ -1073,11 +1129,11 @@ void launch_step(const fif_plan* p, Bound& b, int t, const T* x, T* imfs, void* 
             k_verify<<<(unsigned)((g.ssmall.count + 63) / 64), 64, 0, s>>>(V, g.ssmall.count);
             V.redo_only = 1;
             launch_k_scan<true>(0, g.ssmall.count, sizeof(float) * kScanBinsPerThread * kScanThreads, s, V);
-            k_pass1<MODE_STEP, T, true><<<(unsigned)g.p1.count, kFftThreads, p->lds_p1, s>>>(A, x);
+            run_pass1<MODE_STEP, T, true>(p, (unsigned)g.p1.count, s, A, x);
         }
         A.work = p->d_p2 + g.p2.begin;
         Timed tm(p, "pass2_step", s);
-        k_pass2<MODE_STEP, T, T><<<(unsigned)g.p2.count, kFftThreads, p->lds_p2, s>>>(A, x, imfs, nullptr);
+        run_pass2<MODE_STEP, T, T>(p, (unsigned)g.p2.count, s, A, x, imfs, (T*)nullptr);
     }
     if (g.count.count) {
         Timed tm(p, "count_resid", s);
@@ -1105,11 +1161,11 @@ void launch_final(const fif_plan* p, Bound& b, const T* x, T* rem, int32_t* n_im
         A.work = p->d_p1;
         {
             Timed tm(p, "pass1_rem", s);
-            k_pass1<MODE_REMAINDER, T><<<(unsigned)p->w_p1.size(), kFftThreads, p->lds_p1, s>>>(A, x);
+            run_pass1<MODE_REMAINDER, T>(p, (unsigned)p->w_p1.size(), s, A, x);
         }
         A.work = p->d_p2;
         Timed tm(p, "pass2_rem", s);
-        k_pass2<MODE_REMAINDER, T, T><<<(unsigned)p->w_p2.size(), kFftThreads, p->lds_p2, s>>>(A, x, nullptr, rem);
+        run_pass2<MODE_REMAINDER, T, T>(p, (unsigned)p->w_p2.size(), s, A, x, (T*)nullptr, rem);
     }
 }
 

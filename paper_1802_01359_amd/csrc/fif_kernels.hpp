@@ -315,6 +315,7 @@ struct Lam {
     const double* sinT;   // sin(pi u/N), u <= N/2
     const double* isinT;  // 1/sin(pi u/N), 1 <= u <= N/2
     const double* tab;    // sampled window shape: lambda_j of this step by bin, else null
+    int inl;              // LenPlan::lam_inline
 };
 
 __device__ __forceinline__ Lam make_lam(const LenPlan& lp, const double* dtab, int64_t L, const double* tab)
@@ -328,19 +329,27 @@ __device__ __forceinline__ Lam make_lam(const LenPlan& lp, const double* dtab, i
     w.invL = 1.0 / (double)L;
     w.sinT = dtab + lp.sin_off;
     w.isinT = dtab + lp.isin_off;
+    w.inl = lp.lam_inline;
     return w;
 }
 
+// sin(pi u / N) and 1 / sin(pi u / N) exactly as the table fills compute
+// them, so that a sine evaluated in place equals its table entry bit for bit.
+__device__ __forceinline__ double sin_u(int64_t u, int64_t N) { return sinpi((double)u / (double)N); }
+__device__ __forceinline__ double isin_u(int64_t u, int64_t N) { return 1.0 / sinpi((double)u / (double)N); }
+
 // lambda_j = [sin(pi L j / N) / (L sin(pi j / N))]^4, the DFT of the
 // circulant column of the triangle-squared window, with L*j reduced mod N
-// exactly and both sines read from tables.
+// exactly; the sines come from the tables or are evaluated in place.
 __device__ __forceinline__ double lambda_at(int64_t j, const Lam& w)
 {
     if (j == 0) return 1.0;
     if (w.tab) return w.tab[j];
     int64_t t = w.mask ? ((w.Lmod * j) & w.mask) : mulmod53(w.Lmod, j, w.N, w.invN);
     if (t > w.N - t) t = w.N - t;
-    const double q = w.sinT[t] * w.isinT[j] * w.invL;
+    const double st = w.inl ? sin_u(t, w.N) : w.sinT[t];
+    const double is = w.inl == 2 ? isin_u(j, w.N) : w.isinT[j];
+    const double q = st * is * w.invL;
     const double q2 = q * q;
     return q2 * q2;
 }
@@ -355,7 +364,8 @@ __device__ __forceinline__ float lambda_f32(int64_t j, const Lam& w, float invNf
     if (w.tab) return (float)w.tab[j];
     int64_t t = w.mask ? ((w.Lmod * j) & w.mask) : mulmod53(w.Lmod, j, w.N, w.invN);
     if (t > w.N - t) t = w.N - t;
-    const float q = sinpif((float)t * invNf) * (float)w.isinT[j] * invLf;
+    const float is = w.inl == 2 ? 1.f / sinpif((float)j * invNf) : (float)w.isinT[j];
+    const float q = sinpif((float)t * invNf) * is * invLf;
     const float q2 = q * q;
     return fminf(q2 * q2, 1.f);
 }
@@ -400,13 +410,13 @@ __device__ __forceinline__ double gain_th(double g, double gamma)
 __global__ void k_fill_sin(double* __restrict__ out, int64_t N, int64_t count)
 {
     const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (u < count) out[u] = sinpi((double)u / (double)N);
+    if (u < count) out[u] = sin_u(u, N);
 }
 
 __global__ void k_fill_isin(double* __restrict__ out, int64_t N, int64_t count)
 {
     const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (u < count) out[u] = u == 0 ? 0.0 : 1.0 / sinpi((double)u / (double)N);
+    if (u < count) out[u] = u == 0 ? 0.0 : isin_u(u, N);
 }
 
 // exp(-2 pi i k stride / den) for k < count, written at out[k]
@@ -805,7 +815,10 @@ __global__ void k_fill_specmap(const LenPlan* __restrict__ lpp, int32_t* __restr
 
 // REDO: the pass that recomputes only the signals whose deferred check
 // failed (its own instantiation, so profiles tell it apart).
-template <int MODE, typename InT, bool REDO = false>
+// TILE: largest tile of the plan's lengths (kTileCap, or kTileCapBig when a
+// length needs the wide tiles); it sizes the register staging and the LDS
+// passes.
+template <int MODE, typename InT, bool REDO = false, int TILE = kTileCap>
 __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __restrict__ x)
 {
     extern __shared__ double2 lds[];
@@ -839,7 +852,7 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
             const int owners = TC * (N2 >> 1);
             // the tile's bins are one contiguous run (tile order, see
             // spec_pos); all of a thread's loads are issued first
-            constexpr int PQ = kTileCap / 2 / kFftThreads + 1;
+            constexpr int PQ = TILE / 2 / kFftThreads + 1;
             double2 vv[PQ];
             // deferred FP64 check of m: this tile's part of the stop-test sums,
             // over the bins above the scan's noise floor
@@ -937,9 +950,9 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
     }
     __syncthreads();
     if (fwd_mode(MODE))
-        lds_fft<false, kTileCap>(lds, lp.f1, TC, A.ctab);
+        lds_fft<false, TILE>(lds, lp.f1, TC, A.ctab);
     else
-        lds_fft<true, kTileCap>(lds, lp.f1, TC, A.ctab);
+        lds_fft<true, TILE>(lds, lp.f1, TC, A.ctab);
     double2* Y = A.inter + d.inter_off;
     for (int f = threadIdx.x; f < total; f += kFftThreads) {
         int s;
@@ -962,7 +975,7 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
 // (length N1); output element N2 * c' + r'.  STEP: IMF, one run summary per
 // c' (TR consecutive samples) and the tile's min/max; FORWARD: half
 // spectrum; REMAINDER: y.
-template <int MODE, typename InT, typename OutT>
+template <int MODE, typename InT, typename OutT, int TILE = kTileCap>
 __global__ __launch_bounds__(kFftThreads) void k_pass2(StepArgs A, const InT* __restrict__ x,
                                                        OutT* __restrict__ imfs, OutT* __restrict__ rem)
 {
@@ -1006,7 +1019,7 @@ __global__ __launch_bounds__(kFftThreads) void k_pass2(StepArgs A, const InT* __
         const int TC = lp.TC;
         const FastDiv ftc = fastdiv(TC);
         const int64_t blk = (int64_t)TC * N2;
-        constexpr int GQ = kTileCap / kFftThreads;
+        constexpr int GQ = TILE / kFftThreads;
         double2 yv[GQ];
 #pragma unroll
         for (int q = 0; q < GQ; ++q) {
@@ -1032,9 +1045,9 @@ __global__ __launch_bounds__(kFftThreads) void k_pass2(StepArgs A, const InT* __
     }
     __syncthreads();
     if (fwd_mode(MODE))
-        lds_fft<false, kTileCap>(lds, lp.f2, TR, A.ctab);
+        lds_fft<false, TILE>(lds, lp.f2, TR, A.ctab);
     else
-        lds_fft<true, kTileCap>(lds, lp.f2, TR, A.ctab);
+        lds_fft<true, TILE>(lds, lp.f2, TR, A.ctab);
     if (MODE == MODE_WINDOW) {
         double* lt = A.lam + d.spec_off;
         const double inv = 1.0 / A.wsum[w.sig];
@@ -1069,7 +1082,7 @@ __global__ __launch_bounds__(kFftThreads) void k_pass2(StepArgs A, const InT* __
     OutT* row = imfs + (int64_t)A.max_imfs * d.off + (int64_t)A.t * N;
     // IMF row out of the real parts; the imaginary parts (the residual) are
     // kept in registers
-    constexpr int EQ = kTileCap / kFftThreads;
+    constexpr int EQ = TILE / kFftThreads;
     double yv[EQ];
 #pragma unroll
     for (int q = 0; q < EQ; ++q) {

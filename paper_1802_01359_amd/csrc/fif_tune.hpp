@@ -42,7 +42,7 @@ inline int64_t radix_product(const int8_t* rad, int n)
 // A choice is a valid plan of length N: one LDS pass (N <= kFftCap, N1 = 1,
 // N2 = N, TC = TR = 1, radices of N) or a four-step split N = N1 * N2 with
 // both factors <= kTileCap, tiles that divide their dimension and fit
-// kTileCap elements, and radices of N2 (first list) and N1 (second).
+// kTileCapBig elements, and radices of N2 (first list) and N1 (second).
 inline bool choice_valid(const fif_length_plan& c)
 {
     const int64_t N = c.N;
@@ -52,8 +52,8 @@ inline bool choice_valid(const fif_length_plan& c)
                radix_product(c.rad1, c.n_rad1) == N;
     }
     if (c.N1 < 2 || c.N2 < 2 || c.N1 > kTileCap || c.N2 > kTileCap || (int64_t)c.N1 * c.N2 != N) return false;
-    if (c.TC < 1 || c.N1 % c.TC || (int64_t)c.TC * c.N2 > kTileCap) return false;
-    if (c.TR < 1 || c.N2 % c.TR || (int64_t)c.TR * c.N1 > kTileCap) return false;
+    if (c.TC < 1 || c.N1 % c.TC || (int64_t)c.TC * c.N2 > kTileCapBig) return false;
+    if (c.TR < 1 || c.N2 % c.TR || (int64_t)c.TR * c.N1 > kTileCapBig) return false;
     return radix_product(c.rad1, c.n_rad1) == c.N2 && radix_product(c.rad2, c.n_rad2) == c.N1;
 }
 

@@ -8,6 +8,11 @@ namespace fif {
 constexpr int kFftCap = 8192;
 // Elements of one four-step tile (64 KiB of LDS: two workgroups per CU).
 constexpr int kTileCap = 4096;
+// Elements of a wide four-step tile (128 KiB of LDS, one workgroup per CU):
+// used where the kTileCap tile would hold a single column or row (N1 or N2 =
+// 4096), so that pass-1 tiles can pair mirror columns and read the spectrum
+// in contiguous runs.
+constexpr int kTileCapBig = 8192;
 // Threads of the FFT workgroups and of the scan workgroups.
 constexpr int kFftThreads = 512;
 constexpr int kScanThreads = 512;
@@ -42,7 +47,18 @@ struct LenPlan {
     double invN;                   // 1/N rounded
     int32_t big_split;             // exp(-2 pi i a/N) = hi[a >> shift] * lo[a & (split-1)]
     int32_t big_shift;             // log2(big_split)
+    // where lambda_j's sines come from: 0 both tables; 1 sin(pi t/N), t = L j
+    // mod N, evaluated in place (the table gather at t is a random access per
+    // bin); 2 both sines evaluated in place.  Same values in every case.
+    int32_t lam_inline;
+    int32_t lam_pad;
 };
+
+// Sine-table bytes of a plan (all lengths) up to which lambda_j reads its
+// sines from the tables: beyond, the gathers at L j mod N (random) and at j
+// (runs of a tile's width in pass 1) miss the L2 and both sines are
+// evaluated in place instead.
+constexpr int64_t kSinTableHotBytes = 2 << 20;
 
 // Per signal of the batch.
 struct SigDesc {

@@ -52,7 +52,7 @@ def test_several_entries_and_replacement(tmp_path):
     "FIFTUNE1 gfx950/hip1 65536 128 256 16 8 4.8.8 8.8.4 1.0 2.0",          # N1 N2 != N
     "FIFTUNE1 gfx950/hip1 65536 256 256 16 8 4.8.8 6.8.4 1.0 2.0",          # no radix 6
     "FIFTUNE1 gfx950/hip1 65536 256 256 12 8 4.8.8 8.8.4 1.0 2.0",          # TC does not divide N1
-    "FIFTUNE1 gfx950/hip1 65536 256 256 32 8 4.8.8 8.8.4 1.0 2.0",          # pass-1 tile > 4096 elements
+    "FIFTUNE1 gfx950/hip1 65536 256 256 64 8 4.8.8 8.8.4 1.0 2.0",          # pass-1 tile > 8192 elements
     "FIFTUNE1 gfx950/hip1 65536 256 256 16 8 4.8.8 8.8.4 1.0 2.0 extra",    # trailing field
     "FIFTUNE2 gfx950/hip1 65536 256 256 16 8 4.8.8 8.8.4 1.0 2.0",          # other format
     "FIFTUNE1 gfx950/hip1 65536 256 256 16 8 4.8.8 8.8.x 1.0 2.0",          # radix text
