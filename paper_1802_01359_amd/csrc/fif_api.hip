@@ -113,6 +113,7 @@ struct fif_plan {
     struct Group {
         int32_t s0 = 0, s1 = 0;
         Range single, p1, p2, ssmall, sbig, btile, count;
+        bool big_defer = false;     // a signal of the multi-workgroup search may defer its FP64 check
     };
     std::vector<Group> groups;      // groups[0] is the whole batch when only one
     Group all;
@@ -663,6 +664,8 @@ fif_status create_plan(fif_plan** out, const int64_t* lengths, int32_t B, int32_
             g.count = sub(p->w_count, s0, s1);
             g.ssmall = subi(p->scan_small, s0, s1);
             g.sbig = subi(p->scan_big, s0, s1);
+            for (int32_t i = 0; i < g.sbig.count; ++i)
+                g.big_defer = g.big_defer || p->sigs[p->scan_big[g.sbig.begin + i]].n_btiles <= kBigDeferTiles;
             return g;
         };
         p->all = make_group(0, B);
@@ -1119,16 +1122,40 @@ void launch_step(const fif_plan* p, Bound& b, int t, const T* x, T* imfs, void* 
             Timed tm(p, "pass1_step", s);
             run_pass1<MODE_STEP, T>(p, (unsigned)g.p1.count, s, A, x);
         }
-        if (b.sc.defer && g.ssmall.count) {
+        const unsigned nb = g.big_defer ? (unsigned)g.sbig.count : 0u, nt = (unsigned)g.btile.count;
+        if (b.sc.defer && (g.ssmall.count || nb)) {
             // deferred FP64 check of m, then the rare redo: exact search and
             // pass 1 again for the signals whose check failed
             Timed tm(p, "verify", s);
             ScanArgs V = b.sc;
             V.t = t;
-            V.list = p->d_scan_small + g.ssmall.begin;
-            k_verify<<<(unsigned)((g.ssmall.count + 63) / 64), 64, 0, s>>>(V, g.ssmall.count);
+            const int32_t* small = p->d_scan_small + g.ssmall.begin;
+            const int32_t* big = p->d_scan_big + g.sbig.begin;
+            if (g.ssmall.count) {
+                V.list = small;
+                k_verify<<<(unsigned)((g.ssmall.count + 63) / 64), 64, 0, s>>>(V, g.ssmall.count);
+            }
+            if (nb) {
+                V.list = big;
+                k_verify<<<(nb + 63) / 64, 64, 0, s>>>(V, (int)nb);
+            }
             V.redo_only = 1;
-            launch_k_scan<true>(0, g.ssmall.count, sizeof(float) * kScanBinsPerThread * kScanThreads, s, V);
+            if (g.ssmall.count) {
+                V.list = small;
+                launch_k_scan<true>(0, g.ssmall.count, sizeof(float) * kScanBinsPerThread * kScanThreads, s, V);
+            }
+            if (nb) {
+                // FP64 rounds of the multi-workgroup search for the signals
+                // whose check failed (the others return at once)
+                V.list = big;
+                const Work* btile = p->d_btile + g.btile.begin;
+                k_bscan_redo_prep<<<nb, 64, 0, s>>>(V);
+                for (int r = 0; r < kBigRedoRounds; ++r) {
+                    k_bscan_round<kScanThreads, false><<<nt, kScanThreads, 0, s>>>(V, btile);
+                    k_bscan_decide<<<nb, 64 * kDecideGroups, 0, s>>>(V);
+                }
+                k_bscan_final<kScanThreads><<<nb, 64, 0, s>>>(V);
+            }
             run_pass1<MODE_STEP, T, true>(p, (unsigned)g.p1.count, s, A, x);
         }
         A.work = p->d_p2 + g.p2.begin;

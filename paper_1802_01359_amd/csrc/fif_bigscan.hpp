@@ -418,7 +418,8 @@ __device__ __forceinline__ void bscan_tile_totals(const ScanArgs& A, const SigDe
 
 // Thread 0 of the decide workgroup: update the brackets, choose the next
 // candidates.
-__device__ __forceinline__ void bscan_decide(const ScanArgs& A, const SigDesc& d, BigScan* G, const double* tot)
+__device__ __forceinline__ void bscan_decide(const ScanArgs& A, int s, const SigDesc& d, BigScan* G,
+                                             const double* tot)
 {
     const int nc = G->ncand;
     const double* Asum = tot;          // numerator of candidate i at Asum[2i]
@@ -462,7 +463,27 @@ __device__ __forceinline__ void bscan_decide(const ScanArgs& A, const SigDesc& d
             mt = hi;
         G->lo = lo;
         G->hi = hi;
-        if (mt >= 0) {
+        if (mt >= 0 && mode == 0 && A.defer && d.n_btiles <= kBigDeferTiles) {
+            // the FP64 check of SD_mt <= delta < SD_{mt-1} is left to pass 1,
+            // which forms every bin's gain anyway; k_verify accepts the
+            // estimate or sends the signal to the FP64 rounds of the redo
+            if (A.mt_shift) mt = max((int64_t)1, min(cap, mt + (int64_t)A.mt_shift));
+            G->phase = kBigDeferred;
+            G->mt = mt;
+            SigState* S = A.st + s;
+            S->L = G->L;
+            S->m = mt;
+            S->chk = 1;
+            S->qthr = G->qthr;
+            if (A.info) {
+                fif_imf_info* I = A.info + (int64_t)s * A.max_imfs + A.t;
+                I->k = S->k;
+                I->L = G->L;
+                I->m = mt;
+                I->flags = 0;
+                I->evals = (G->n32 & 0xffffu) | (1u << 16);
+            }
+        } else if (mt >= 0) {
             // FP64 confirmation of SD_mt <= delta < SD_{mt-1}
             G->phase = 2;
             G->mt = mt;
@@ -558,6 +579,7 @@ __global__ __launch_bounds__(T) void k_bscan_round(ScanArgs A, const Work* __res
         // position -> bin table of this length, read once (null: bin order)
         const int32_t* btab = lp.spec_perm ? A.itab + lp.bin_off : nullptr;
         const double pscale = G->pscale;
+        const float invNf = 1.f / (float)d.N, invLf = 1.f / (float)G->L;
         double qmx = 0.0;      // largest |R_j|^2 of the tile (noise floor of the FP64 phase)
         constexpr int SG = 4;  // bins whose loads are issued together
         for (int q0 = 0; q0 < BPT; q0 += SG) {
@@ -581,10 +603,14 @@ __global__ __launch_bounds__(T) void k_bscan_round(ScanArgs A, const Work* __res
             const int64_t jb = jj[g];                  // its bin
             qmx = fmax(qmx, z.x * z.x + z.y * z.y);
             const double P = ((2 * jb == d.N) ? 1.0 : 2.0) * (z.x * z.x + z.y * z.y) * pscale;
-            const double lam = lambda_at(jb, lw);
-            bv[j - 1] = (float)P;
-            av[j - 1] = (float)(P * lam * lam);
-            tau[j - 1] = 2.8853900817779268f * log1pf(-(float)lam);
+            // lambda in FP32, as in k_scan: these values only bracket m (both
+            // sines from sinpif: the bins come in storage order, and these
+            // lengths' tables are large)
+            const float lf = lambda_f32<true>(jb, lw, invNf, invLf);
+            const float pf = (float)P;
+            bv[j - 1] = pf;
+            av[j - 1] = pf * lf * lf;
+            tau[j - 1] = 2.8853900817779268f * log1pf(-lf);
           }
         }
         double mn_unused = INFINITY;
@@ -604,19 +630,24 @@ __global__ __launch_bounds__(64 * kDecideGroups) void k_bscan_decide(ScanArgs A)
     __shared__ double part[64 * kDecideGroups];
     __shared__ double partm[64 * kDecideGroups];
     __shared__ double tot[2 * kBigCand];
+    __shared__ double shq[2 * kDecideGroups];
     const int s = A.list[blockIdx.x];
     const SigDesc d = A.sigs[s];
     BigScan* G = A.bigs + d.bs;
     if (G->phase >= 3) return;
+    // after the sweep: the tiles' largest |R_j|^2 (all threads)
+    const bool first = G->phase < 2 && G->n32 == 0;
+    double q = 0.0, mn_unused = INFINITY;
+    if (first)
+        for (int t = threadIdx.x; t < d.n_btiles; t += 64 * kDecideGroups) q = fmax(q, A.bqmax[d.bt_off + t]);
+    block_minmax<64 * kDecideGroups>(mn_unused, q, shq);
     bscan_tile_totals(A, d, G->ncand, G->phase >= 2, part, partm, tot);
     __syncthreads();
     if (threadIdx.x == 0) {
         bool skip = false;       // stop mode 2: this round only found N0
-        if (G->phase < 2 && G->n32 == 0) {
-            // after the sweep: the tiles' largest |R_j|^2 give the noise floor
-            // of the relative test, or Theorem 5's N0 (with the DC bin)
-            double q = 0.0;
-            for (int t = 0; t < d.n_btiles; ++t) q = fmax(q, A.bqmax[d.bt_off + t]);
+        if (first) {
+            // the tiles' largest |R_j|^2 give the noise floor of the
+            // relative test, or Theorem 5's N0 (with the DC bin)
             G->qthr = A.stop_mode == 0 ? kSdNoise * q : 0.0;
             G->mt = 0;
             if (A.stop_mode != 0) {
@@ -638,8 +669,35 @@ __global__ __launch_bounds__(64 * kDecideGroups) void k_bscan_decide(ScanArgs A)
                 }
             }
         }
-        if (!skip) bscan_decide(A, d, G, tot);
+        if (!skip) bscan_decide(A, s, d, G, tot);
     }
+}
+
+// After k_verify: a deferred signal whose check failed goes back to the FP64
+// phase, first with the kBigRedoCand consecutive counts around its estimate
+// (gallop and refinement follow if the answer lies outside them); the others
+// stay deferred (their estimate stands, k_bscan_final leaves them alone).
+constexpr int kBigRedoCand = 8;
+__global__ void k_bscan_redo_prep(ScanArgs A)
+{
+    if (threadIdx.x != 0) return;
+    const int s = A.list[blockIdx.x];
+    const SigDesc d = A.sigs[s];
+    BigScan* G = A.bigs + d.bs;
+    SigState* S = A.st + s;
+    if (G->phase != kBigDeferred || !S->redo) return;
+    const int64_t cap = A.max_inner;
+    const int64_t lo = max((int64_t)1, min(cap - kBigRedoCand + 1, G->mt - kBigRedoCand / 2));
+    int n = 0;
+    for (int64_t c = lo; c <= cap && n < kBigRedoCand; ++c) G->cand[n++] = c;
+    G->ncand = n;
+    G->phase = 2;
+    G->elo = 0;
+    G->ehi = -1;
+    G->sd_lo = INFINITY;
+    G->sd_hi = 0.0;
+    G->n64 = 0;
+    G->flags |= FIF_IMF_REFINED;
 }
 
 template <int T>
@@ -650,7 +708,7 @@ __global__ __launch_bounds__(T) void k_bscan_final(ScanArgs A)
     const SigDesc d = A.sigs[s];
     SigState* S = A.st + s;
     BigScan* G = A.bigs + d.bs;
-    if (G->phase == kBigInactive) return;
+    if (G->phase == kBigInactive || G->phase == kBigDeferred) return;
     uint32_t flags = G->flags;
     if (G->phase != 3) {
         // out of rounds (not expected): keep the FP64-verified upper end

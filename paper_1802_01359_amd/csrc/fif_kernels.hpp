@@ -357,14 +357,16 @@ __device__ __forceinline__ double lambda_at(int64_t j, const Lam& w)
 // lambda_j in FP32 for the FP32 search for m (the FP64 lambda_at decides
 // everywhere else): the reduced argument t = L j mod N is exact as before,
 // sin(pi t / N) comes from sinpif instead of a table gather (a random access
-// per bin), 1 / sin(pi j / N) from the table (read in bin order).
+// per bin), 1 / sin(pi j / N) from the table (ISIN = false: read in bin
+// order) or from sinpif too (ISIN = true).
+template <bool ISIN = false>
 __device__ __forceinline__ float lambda_f32(int64_t j, const Lam& w, float invNf, float invLf)
 {
     if (j == 0) return 1.f;
     if (w.tab) return (float)w.tab[j];
     int64_t t = w.mask ? ((w.Lmod * j) & w.mask) : mulmod53(w.Lmod, j, w.N, w.invN);
     if (t > w.N - t) t = w.N - t;
-    const float is = w.inl == 2 ? 1.f / sinpif((float)j * invNf) : (float)w.isinT[j];
+    const float is = ISIN ? 1.f / sinpif((float)j * invNf) : (float)w.isinT[j];
     const float q = sinpif((float)t * invNf) * is * invLf;
     const float q2 = q * q;
     return fminf(q2 * q2, 1.f);
@@ -901,7 +903,7 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
                         g = y * om;
                     }
                     if (chk && v.x * v.x + v.y * v.y >= qthr) {
-                        const double P = ((2 * k == N) ? 1.0 : 2.0) * (v.x * v.x + v.y * v.y);
+                        const double P = ((k == 0 || 2 * k == N) ? 1.0 : 2.0) * (v.x * v.x + v.y * v.y);
                         const double l2 = lam * lam;
                         cs[0] += P * l2 * y * y;
                         cs[1] += P * y * y;
@@ -934,6 +936,11 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
             }
         } else {
             const int64_t nh = N / 2;
+            // deferred FP64 check as in the paired tiles, each bin counted at
+            // its own element (k <= N/2), not at its mirror
+            const bool chk = MODE == MODE_STEP && S->chk;
+            const double qthr = chk ? S->qthr : 0.0;
+            double cs[4] = {0.0, 0.0, 0.0, 0.0};
             for (int f = threadIdx.x; f < total; f += kFftThreads) {
                 int s;
                 const int r = fdivmod(f, ftc, s);
@@ -942,9 +949,44 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
                 const int64_t j = mirror ? N - k : k;
                 const double2 v = Rin[j];
                 double g = 0.0;
-                if (MODE == MODE_STEP) g = gain_th(gain_pow(lambda_at(j, lw), m), A.gamma);
+                if (MODE == MODE_STEP) {
+                    const double lam = lambda_at(j, lw);
+                    if (chk) {
+                        // (1-lambda)^m from (1-lambda)^(m-2), as in the paired tiles
+                        double y, z;
+                        if (lam >= 1.0) {
+                            y = (m == 1) ? 1.0 : 0.0;
+                            z = (m == 2) ? 1.0 : 0.0;
+                            g = 0.0;
+                        } else {
+                            const double om = 1.0 - lam;
+                            z = (m >= 2) ? ((m == 2) ? 1.0 : gain_pow(lam, m - 2)) : 0.0;
+                            y = (m >= 2) ? z * om : 1.0;
+                            g = y * om;
+                        }
+                        if (!mirror && v.x * v.x + v.y * v.y >= qthr) {
+                            const double P = ((j == 0 || 2 * j == N) ? 1.0 : 2.0) * (v.x * v.x + v.y * v.y);
+                            const double l2 = lam * lam;
+                            cs[0] += P * l2 * y * y;
+                            cs[1] += P * y * y;
+                            cs[2] += P * l2 * z * z;
+                            cs[3] += P * z * z;
+                        }
+                    } else {
+                        g = gain_pow(lam, m);
+                    }
+                    g = gain_th(g, A.gamma);
+                }
                 lds[f] = step_input(v, mirror, g, invN);
                 if (MODE == MODE_STEP && !mirror) Rout[j] = cscale(v, 1.0 - g);
+            }
+            if (chk) {
+                __shared__ double shu[4 * (kFftThreads / 64)];
+                block_sum<double, kFftThreads, 4>(cs, shu);
+                if (threadIdx.x < 4) {
+                    const double cv = threadIdx.x == 0 ? cs[0] : threadIdx.x == 1 ? cs[1] : threadIdx.x == 2 ? cs[2] : cs[3];
+                    A.chk[((int64_t)d.p1_off + w.tile) * 4 + threadIdx.x] = cv;
+                }
             }
         }
     }
@@ -1596,10 +1638,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
         }
     }
 
-    // ---- deferred FP64 check: paired four-step signals leave it to pass 1,
+    // ---- deferred FP64 check: four-step signals leave it to pass 1,
     //      which reads the spectrum and forms the powers anyway; k_verify
     //      accepts the estimate or sends the signal back here (redo_only)
-    if (SMODE == 0 && A.defer && !A.redo_only && lp.two_pass && lp.paired) {
+    if (SMODE == 0 && A.defer && !A.redo_only && lp.two_pass) {
         if (A.mt_shift) mt = max((int64_t)1, min(cap, mt + (int64_t)A.mt_shift));
         // the check in pass 1 counts the same bins as the FP64 evaluation here
         double mn_unused = INFINITY, qm = mz;

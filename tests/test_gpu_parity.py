@@ -337,11 +337,14 @@ def test_long_signal_full_size():
 @pytest.mark.parametrize("shift", [1, -1])
 def test_deferred_check_redo_path(shift, monkeypatch):
     """The FP64 check of m for four-step signals runs inside pass 1; when it
-    fails the step is redone (exact search, pass 1 again). A host-side hook
-    shifts every deferred estimate so that every check fails: decisions must
-    equal the unshifted run's and the oracle's, and every IMF is flagged as
-    refined."""
-    lengths = [65536, 65536, 16384, 4096, 12000]
+    fails the step is redone (exact search, pass 1 again; for signals of the
+    multi-workgroup search its FP64 rounds). A host-side hook shifts every
+    deferred estimate so that every check fails: decisions must equal the
+    unshifted run's and the oracle's, and every IMF is flagged as refined
+    (but m = 1 shifted down, which stays 1 and passes).  Lengths: paired and
+    unpaired four-step plans (10125 = 3^4 5^3), and the multi-workgroup search
+    with paired (131072) and unpaired (98415 = 3^9 5) plans."""
+    lengths = [65536, 65536, 16384, 4096, 12000, 10125, 131072, 98415]
     sigs = [siggen.chirps(i).astype(np.float32) if N == 65536 else _signal(N, 900 + i).astype(np.float32)
             for i, N in enumerate(lengths)]
     print("case deferred check shift=%d" % shift, flush=True)
@@ -357,7 +360,8 @@ def test_deferred_check_redo_path(shift, monkeypatch):
         four_step = N > 8192
         valid = np.arange(6) < n1[b]
         if four_step:
-            assert np.all(i1["flags"][b][valid] & fif.IMF_REFINED)
+            refined = (i1["flags"][b][valid] & fif.IMF_REFINED) != 0
+            assert np.all(refined | ((shift < 0) & (i1["m"][b][valid] == 1))), (N, i1["flags"][b][valid])
         a = ref.imfs_of(b).double()
         c = out.imfs_of(b).double()
         assert float((a - c).norm()) <= 1e-6 * float(a.norm())
