@@ -189,9 +189,10 @@ typedef struct {
 /*
  * fif_plan_create with plans picked by measurement.  For every distinct
  * length above 8192 the library times candidate choices -- the three most
- * balanced splits N1 * N2, the widest pass-1 and pass-2 tiles and half of
- * each, the built-in radix order and its reverse; the built-in choice is
- * one of them -- by decomposing a synthetic batch of that length (two IMFs)
+ * balanced splits N1 * N2 (and the most balanced one with both factors even,
+ * which mirror-paired pass-1 tiles need), the widest pass-1 and pass-2 tiles
+ * and half of each (and the widest even pass-1 tile), the built-in radix
+ * order and its reverse; the built-in choice is one of them -- by decomposing a synthetic batch of that length (two IMFs)
  * with each, and keeps the fastest.  Results are cached in the text file
  * tune_cache (NULL: the file named by the environment variable
  * FIF_TUNE_CACHE; NULL and unset: no cache) under a key made of the

@@ -1272,8 +1272,9 @@ __global__ void k_tune_signal(float* __restrict__ x, int64_t total, int64_t N)
 // Largest divisor of n that is at most cap (>= 1).
 int64_t divisor_at_most(int64_t n, int64_t cap) { return largest_divisor_at_most(n, std::max<int64_t>(1, cap)); }
 
-// Candidate choices for a two-pass length: the three most balanced splits,
-// the widest pass-1 / pass-2 tiles and half of each, the built-in radix order
+// Candidate choices for a two-pass length: the three most balanced splits
+// (and the most balanced even-even one), the widest pass-1 / pass-2 tiles and
+// half of each (and the widest even pass-1 tile), the built-in radix order
 // and its reverse.  The built-in choice comes first.
 std::vector<fif_length_plan> tune_candidates(int64_t N)
 {
@@ -1292,18 +1293,35 @@ std::vector<fif_length_plan> tune_candidates(int64_t N)
         const int64_t ma = std::max(a.first, a.second), mb = std::max(b.first, b.second);
         return ma != mb ? ma < mb : a.second > b.second;
     });
+    // the most balanced split whose factors are both even (mirror-paired
+    // pass-1 tiles need it) joins the three most balanced ones
+    auto even = [](const std::pair<int64_t, int64_t>& sp) { return sp.first % 2 == 0 && sp.second % 2 == 0; };
+    const auto ev = std::find_if(splits.begin(), splits.end(), even);
+    const bool add_even = ev != splits.end() && std::none_of(splits.begin(), splits.begin() + std::min<size_t>(3, splits.size()), even);
+    const std::pair<int64_t, int64_t> even_split = add_even ? *ev : std::pair<int64_t, int64_t>(0, 0);
     if (splits.size() > 3) splits.resize(3);
+    if (add_even) splits.push_back(even_split);
     for (const auto& sp : splits) {
         const int64_t N1 = sp.first, N2 = sp.second;
         SubFft f1, f2;
         if (!make_subfft(N2, f1) || !make_subfft(N1, f2)) continue;
         const int64_t tc0 = divisor_at_most(N1, kTileCap / N2), tr0 = divisor_at_most(N2, kTileCap / N1);
-        const int64_t tcs[2] = {tc0, divisor_at_most(N1, tc0 / 2)};
+        // pass-1 tile widths: the widest, half of it, and the widest even one
+        // (paired tiles) when both factors are even
+        int64_t tce = 0;
+        if (even(sp))
+            for (int64_t t = kTileCap / N2; t >= 2; --t)
+                if (t % 2 == 0 && N1 % t == 0) {
+                    tce = t;
+                    break;
+                }
+        const int64_t tcs[3] = {tc0, divisor_at_most(N1, tc0 / 2), tce};
         const int64_t trs[2] = {tr0, divisor_at_most(N2, tr0 / 2)};
         for (int rev = 0; rev < 2; ++rev)
-            for (int a = 0; a < 2; ++a)
+            for (int a = 0; a < 3; ++a)
                 for (int b = 0; b < 2; ++b) {
                     if ((a == 1 && tcs[1] == tcs[0]) || (b == 1 && trs[1] == trs[0])) continue;
+                    if (a == 2 && (tcs[2] == 0 || tcs[2] == tcs[0] || tcs[2] == tcs[1])) continue;
                     fif_length_plan c;
                     std::memset(&c, 0, sizeof(c));
                     c.N = N;
