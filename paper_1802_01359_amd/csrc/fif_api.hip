@@ -126,6 +126,7 @@ struct fif_plan {
     std::vector<uintptr_t> gkey;
     size_t lds_single = 0, lds_p1 = 0, lds_p2 = 0;
     bool wide = false;              // a length uses tiles above kTileCap elements
+    bool pow2 = false;              // every four-step length has radices 2, 4, 8 only
     // device copies (one allocation)
     DevBuf dmeta, dtabs;
     SigDesc* d_sigs = nullptr;
@@ -263,6 +264,18 @@ fif_status set_lds_limits()
         set((const void*)k_pass2<MODE_FORWARD, double, double, kTileCapBig>);
         set((const void*)k_pass2<MODE_STEP, double, double, kTileCapBig>);
         set((const void*)k_pass2<MODE_REMAINDER, double, double, kTileCapBig>);
+        set((const void*)k_pass1<MODE_STEP, float, false, kTileCap, true>);
+        set((const void*)k_pass1<MODE_STEP, float, true, kTileCap, true>);
+        set((const void*)k_pass1<MODE_STEP, double, false, kTileCap, true>);
+        set((const void*)k_pass1<MODE_STEP, double, true, kTileCap, true>);
+        set((const void*)k_pass1<MODE_STEP, float, false, kTileCapBig, true>);
+        set((const void*)k_pass1<MODE_STEP, float, true, kTileCapBig, true>);
+        set((const void*)k_pass1<MODE_STEP, double, false, kTileCapBig, true>);
+        set((const void*)k_pass1<MODE_STEP, double, true, kTileCapBig, true>);
+        set((const void*)k_pass2<MODE_STEP, float, float, kTileCap, true>);
+        set((const void*)k_pass2<MODE_STEP, double, double, kTileCap, true>);
+        set((const void*)k_pass2<MODE_STEP, float, float, kTileCapBig, true>);
+        set((const void*)k_pass2<MODE_STEP, double, double, kTileCapBig, true>);
         set((const void*)k_scan<kScanBinsPerThread, false, 0>);
         set((const void*)k_scan<kScanBinsPerThread, true, 0>);
         set((const void*)k_scan<kScanBinsPerThread, false, 1>);
@@ -568,6 +581,7 @@ fif_status create_plan(fif_plan** out, const int64_t* lengths, int32_t B, int32_
 
     // signals, work lists, workspace sizes
     int64_t off = 0, spec = 0, inter = 0, inter_max = 0, gscr = 0, resid = 0;
+    bool any_odd = false, any_two_pass = false;
     int32_t parts = 0, nbig = 0, btiles = 0;
     for (int32_t b = 0; b < B; ++b) {
         const int64_t N = lengths[b];
@@ -621,6 +635,11 @@ fif_status create_plan(fif_plan** out, const int64_t* lengths, int32_t B, int32_
             p->lds_p1 = std::max(p->lds_p1, (size_t)lp.TC * lp.N2 * sizeof(double2));
             p->lds_p2 = std::max(p->lds_p2, (size_t)lp.TR * lp.N1 * sizeof(double2));
             if ((int64_t)lp.TC * lp.N2 > kTileCap || (int64_t)lp.TR * lp.N1 > kTileCap) p->wide = true;
+            bool r248 = true;
+            for (int i = 0; i < lp.f1.nrad; ++i) r248 = r248 && (lp.f1.rad[i] == 2 || lp.f1.rad[i] == 4 || lp.f1.rad[i] == 8);
+            for (int i = 0; i < lp.f2.nrad; ++i) r248 = r248 && (lp.f2.rad[i] == 2 || lp.f2.rad[i] == 4 || lp.f2.rad[i] == 8);
+            if (!r248) any_odd = true;
+            any_two_pass = true;
         }
         if (d.bs < 0)
             p->scan_small.push_back(b);
@@ -629,6 +648,7 @@ fif_status create_plan(fif_plan** out, const int64_t* lengths, int32_t B, int32_
     }
 
     inter = inter_max;
+    p->pow2 = any_two_pass && !any_odd;
 
     // signal groups of about equal sample counts
     {
@@ -929,22 +949,40 @@ Bound bind(const fif_plan* p, void* ws, double delta, fif_imf_info* info)
 }
 
 // Four-step passes with the plan's tile size.
+// (The outer steps' passes also have variants without the odd radices, for
+// plans whose lengths need none.)
 template <int MODE, typename T, bool REDO = false>
 void run_pass1(const fif_plan* p, unsigned grid, hipStream_t s, const StepArgs& A, const T* x)
 {
-    if (p->wide)
-        k_pass1<MODE, T, REDO, kTileCapBig><<<grid, kFftThreads, p->lds_p1, s>>>(A, x);
-    else
-        k_pass1<MODE, T, REDO, kTileCap><<<grid, kFftThreads, p->lds_p1, s>>>(A, x);
+    constexpr bool STEP = MODE == MODE_STEP;
+    if (p->wide) {
+        if (STEP && p->pow2)
+            k_pass1<MODE, T, REDO, kTileCapBig, STEP><<<grid, kFftThreads, p->lds_p1, s>>>(A, x);
+        else
+            k_pass1<MODE, T, REDO, kTileCapBig><<<grid, kFftThreads, p->lds_p1, s>>>(A, x);
+    } else {
+        if (STEP && p->pow2)
+            k_pass1<MODE, T, REDO, kTileCap, STEP><<<grid, kFftThreads, p->lds_p1, s>>>(A, x);
+        else
+            k_pass1<MODE, T, REDO, kTileCap><<<grid, kFftThreads, p->lds_p1, s>>>(A, x);
+    }
 }
 template <int MODE, typename InT, typename OutT>
 void run_pass2(const fif_plan* p, unsigned grid, hipStream_t s, const StepArgs& A, const InT* x, OutT* imfs,
                OutT* rem)
 {
-    if (p->wide)
-        k_pass2<MODE, InT, OutT, kTileCapBig><<<grid, kFftThreads, p->lds_p2, s>>>(A, x, imfs, rem);
-    else
-        k_pass2<MODE, InT, OutT, kTileCap><<<grid, kFftThreads, p->lds_p2, s>>>(A, x, imfs, rem);
+    constexpr bool STEP = MODE == MODE_STEP;
+    if (p->wide) {
+        if (STEP && p->pow2)
+            k_pass2<MODE, InT, OutT, kTileCapBig, STEP><<<grid, kFftThreads, p->lds_p2, s>>>(A, x, imfs, rem);
+        else
+            k_pass2<MODE, InT, OutT, kTileCapBig><<<grid, kFftThreads, p->lds_p2, s>>>(A, x, imfs, rem);
+    } else {
+        if (STEP && p->pow2)
+            k_pass2<MODE, InT, OutT, kTileCap, STEP><<<grid, kFftThreads, p->lds_p2, s>>>(A, x, imfs, rem);
+        else
+            k_pass2<MODE, InT, OutT, kTileCap><<<grid, kFftThreads, p->lds_p2, s>>>(A, x, imfs, rem);
+    }
 }
 
 template <typename T>

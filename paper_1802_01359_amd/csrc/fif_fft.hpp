@@ -225,7 +225,9 @@ __device__ __forceinline__ void fft_pass(double2* __restrict__ buf, int n, int b
 
 // Transform `batch` interleaved sequences of length f.n in place
 // (f.n * batch <= CAP).  Caller must __syncthreads() after filling buf.
-template <bool INV, int CAP>
+// P2: the plan has radices 2, 4 and 8 only (kernels without the odd-radix
+// passes need fewer registers).
+template <bool INV, int CAP, bool P2 = false>
 __device__ __forceinline__ void lds_fft(double2* __restrict__ buf, const SubFft& f, int batch,
                                         const double2* __restrict__ twbase)
 {
@@ -233,13 +235,21 @@ __device__ __forceinline__ void lds_fft(double2* __restrict__ buf, const SubFft&
     int ns = 1;
     for (int p = 0; p < f.nrad; ++p) {
         const int R = f.rad[p];
-        switch (R) {
-        case 2: fft_pass<2, INV, CAP>(buf, f.n, batch, ns, tw); break;
-        case 3: fft_pass<3, INV, CAP>(buf, f.n, batch, ns, tw); break;
-        case 4: fft_pass<4, INV, CAP>(buf, f.n, batch, ns, tw); break;
-        case 5: fft_pass<5, INV, CAP>(buf, f.n, batch, ns, tw); break;
-        case 7: fft_pass<7, INV, CAP>(buf, f.n, batch, ns, tw); break;
-        default: fft_pass<8, INV, CAP>(buf, f.n, batch, ns, tw); break;
+        if (P2) {
+            switch (R) {
+            case 2: fft_pass<2, INV, CAP>(buf, f.n, batch, ns, tw); break;
+            case 4: fft_pass<4, INV, CAP>(buf, f.n, batch, ns, tw); break;
+            default: fft_pass<8, INV, CAP>(buf, f.n, batch, ns, tw); break;
+            }
+        } else {
+            switch (R) {
+            case 2: fft_pass<2, INV, CAP>(buf, f.n, batch, ns, tw); break;
+            case 3: fft_pass<3, INV, CAP>(buf, f.n, batch, ns, tw); break;
+            case 4: fft_pass<4, INV, CAP>(buf, f.n, batch, ns, tw); break;
+            case 5: fft_pass<5, INV, CAP>(buf, f.n, batch, ns, tw); break;
+            case 7: fft_pass<7, INV, CAP>(buf, f.n, batch, ns, tw); break;
+            default: fft_pass<8, INV, CAP>(buf, f.n, batch, ns, tw); break;
+            }
         }
         tw += ns;
         ns *= R;

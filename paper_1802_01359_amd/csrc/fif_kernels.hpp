@@ -820,7 +820,7 @@ __global__ void k_fill_specmap(const LenPlan* __restrict__ lpp, int32_t* __restr
 // TILE: largest tile of the plan's lengths (kTileCap, or kTileCapBig when a
 // length needs the wide tiles); it sizes the register staging and the LDS
 // passes.
-template <int MODE, typename InT, bool REDO = false, int TILE = kTileCap>
+template <int MODE, typename InT, bool REDO = false, int TILE = kTileCap, bool P2 = false>
 __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __restrict__ x)
 {
     extern __shared__ double2 lds[];
@@ -992,9 +992,9 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
     }
     __syncthreads();
     if (fwd_mode(MODE))
-        lds_fft<false, TILE>(lds, lp.f1, TC, A.ctab);
+        lds_fft<false, TILE, P2>(lds, lp.f1, TC, A.ctab);
     else
-        lds_fft<true, TILE>(lds, lp.f1, TC, A.ctab);
+        lds_fft<true, TILE, P2>(lds, lp.f1, TC, A.ctab);
     double2* Y = A.inter + d.inter_off;
     for (int f = threadIdx.x; f < total; f += kFftThreads) {
         int s;
@@ -1017,7 +1017,7 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
 // (length N1); output element N2 * c' + r'.  STEP: IMF, one run summary per
 // c' (TR consecutive samples) and the tile's min/max; FORWARD: half
 // spectrum; REMAINDER: y.
-template <int MODE, typename InT, typename OutT, int TILE = kTileCap>
+template <int MODE, typename InT, typename OutT, int TILE = kTileCap, bool P2 = false>
 __global__ __launch_bounds__(kFftThreads) void k_pass2(StepArgs A, const InT* __restrict__ x,
                                                        OutT* __restrict__ imfs, OutT* __restrict__ rem)
 {
@@ -1087,9 +1087,9 @@ __global__ __launch_bounds__(kFftThreads) void k_pass2(StepArgs A, const InT* __
     }
     __syncthreads();
     if (fwd_mode(MODE))
-        lds_fft<false, TILE>(lds, lp.f2, TR, A.ctab);
+        lds_fft<false, TILE, P2>(lds, lp.f2, TR, A.ctab);
     else
-        lds_fft<true, TILE>(lds, lp.f2, TR, A.ctab);
+        lds_fft<true, TILE, P2>(lds, lp.f2, TR, A.ctab);
     if (MODE == MODE_WINDOW) {
         double* lt = A.lam + d.spec_off;
         const double inv = 1.0 / A.wsum[w.sig];
