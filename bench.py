@@ -197,6 +197,34 @@ def cpu_baseline(sigs, delta, max_imfs, count: int, threads: int, window=None, o
     return decs, sum(len(s) for s in batch), el
 
 
+def lane_mismatch(a, b, lengths, J) -> dict:
+    """Decision agreement of the FP32 lane's result a with the FP64 path's b
+    on the same batch: signals whose decisions all agree, IMFs that agree up
+    to a signal's first difference, and the largest relative L2 difference of
+    those IMFs."""
+    ia, ib = a.info(), b.info()
+    na, nb = a.n_imfs.cpu().numpy(), b.n_imfs.cpu().numpy()
+    sig_same = imf_same = 0
+    worst = 0.0
+    for s in range(len(lengths)):
+        j = 0
+        while j < min(na[s], nb[s]) and all(ia[k][s][j] == ib[k][s][j] for k in ("k", "L", "m")):
+            j += 1
+        imf_same += j
+        sig_same += (j == nb[s] and na[s] == nb[s])
+        if j:
+            xa, xb = a.imfs_of(s)[:j].double(), b.imfs_of(s)[:j].double()
+            e = ((xa - xb).norm(dim=1) / xb.norm(dim=1).clamp_min(1e-300)).max()
+            worst = max(worst, float(e))
+    ma = np.arange(J)[None, :] < na[:, None]
+    return {"signals_with_fp64_decisions": int(sig_same), "signals": len(lengths),
+            "imfs_with_fp64_decisions": int(imf_same), "imfs": int(nb.sum()),
+            "decision_mismatch_rate_signals": round(float(1.0 - sig_same / len(lengths)), 4),
+            "max_imf_rel_l2_where_decisions_agree": worst,
+            "imfs_per_signal": round(float(na.mean()), 3), "fp64_imfs_per_signal": round(float(nb.mean()), 3),
+            "m_median": int(np.median(ia["m"][ma])), "m_max": int(ia["m"][ma].max())}
+
+
 def parity_of(decs, sigs, out, J, esize):
     """Decisions and per-IMF relative L2 error of the GPU output `out` for the
     signals the CPU oracle decomposed (signal b = decs[b])."""
@@ -378,6 +406,24 @@ def main():
             log("plain single-signal form %.3g samples/s, learned proposal %.3g samples/s (identical %s)" % (
                 forms["plain_form"]["value"], forms["learned_form"]["value"],
                 forms["learned_form"]["identical_to_plain_search"]))
+            # the FP32 lane on the same batch: its speed and how often its
+            # decisions differ from the FP64 path's (which are the oracle's)
+            aplan = fif.Plan(lengths, J, fif.Options(precision=fif.PREC_FP32),
+                             tune_cache=None if args.no_tune else args.tune_cache)
+            if not args.no_tune:
+                plans["fp32_lane_choice"] = {k: aplan.length_plan(lengths[0])[k] for k in ("N1", "N2", "TC", "TR")}
+            ao = aplan.alloc_outputs(dt)
+            aplan.run(packed, delta, out=ao)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(args.steps):
+                aplan.run(packed, delta, out=ao)
+            torch.cuda.synchronize()
+            el_a = time.perf_counter() - t1
+            forms["fp32_lane"] = dict(value=total * args.steps / el_a, ms_per_step=1e3 * el_a / args.steps,
+                                      **lane_mismatch(ao, out, lengths, J))
+            log("FP32 lane %.3g samples/s: %s" % (forms["fp32_lane"]["value"], forms["fp32_lane"]))
+            del aplan, ao
         extra = {}
         if model is not None:
             # the same batch with the plain search, for comparison

@@ -132,8 +132,21 @@ typedef struct {
                             triangle's zero eigenvalues).  Shape {1, 0} is the
                             triangle itself. */
     int32_t window_points;
-    int32_t reserved;
+    int32_t precision;   /* FIF_PREC_MIXED (default): transforms and stored
+                            spectra in FP64, the residual whose extrema are
+                            counted FP64 -- the form whose decisions match the
+                            FP64 oracle.  FIF_PREC_FP32: transforms, stored
+                            spectra and the four-step intermediate in FP32
+                            (half the traffic); lambda, (1 - lambda)^m and the
+                            stop-test sums stay FP64.  No parity claim: the
+                            FP32 residual's rounding can add or remove extrema
+                            and so change k, L, m or the IMF count.  Not with
+                            a window shape or a proposal network. */
 } fif_options;
+
+/* fif_options.precision */
+#define FIF_PREC_MIXED 0
+#define FIF_PREC_FP32 1
 
 typedef struct {
     int64_t k;           /* extrema count of the residual the IMF came from */
@@ -196,7 +209,8 @@ typedef struct {
  * with each, and keeps the fastest.  Results are cached in the text file
  * tune_cache (NULL: the file named by the environment variable
  * FIF_TUNE_CACHE; NULL and unset: no cache) under a key made of the
- * device's architecture name and the HIP runtime version; cached lengths are
+ * device's architecture name and the HIP runtime version (and "/fp32" for
+ * the FP32 lane, whose choices are kept apart); cached lengths are
  * not timed again.  Shorter lengths take the built-in choice.  Tuning
  * allocates and runs kernels on the current device and synchronises it.
  */

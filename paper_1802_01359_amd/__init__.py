@@ -18,13 +18,13 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from ._binding import (EXPORTED, IMF_CAP, STATIC_WORKSPACE_BYTES, LengthPlan, IMF_INFO_DTYPE, IMF_REFINED, NET_CHANNELS, NET_FEATURES, NET_PARAMS,
+from ._binding import (EXPORTED, IMF_CAP, PREC_FP32, PREC_MIXED, STATIC_WORKSPACE_BYTES, LengthPlan, IMF_INFO_DTYPE, IMF_REFINED, NET_CHANNELS, NET_FEATURES, NET_PARAMS,
                        FifError, Options, check, load, LIB_PATH, STOP_FAILED, STOP_FEW_EXTREMA, STOP_FLOOR,
                        STOP_MAX_IMFS)
 
 __all__ = ["Options", "Plan", "BatchResult", "Decomposition", "decompose", "FifError", "IMF_CAP",
            "IMF_REFINED", "IMF_INFO_DTYPE", "EXPORTED", "LIB_PATH", "load", "Model", "NET_PARAMS",
-           "NET_FEATURES", "NET_CHANNELS"]
+           "NET_FEATURES", "NET_CHANNELS", "PREC_MIXED", "PREC_FP32"]
 
 
 def _torch():

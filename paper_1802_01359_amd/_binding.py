@@ -30,6 +30,9 @@ STATIC_WORKSPACE_BYTES = 64 << 20
 IMF_CAP = 1
 IMF_REFINED = 2
 
+# fif_options.precision
+PREC_MIXED, PREC_FP32 = 0, 1
+
 STOP_MAX_IMFS, STOP_FLOOR, STOP_FEW_EXTREMA, STOP_FAILED = 0, 1, 2, 3
 
 # symbols declared in include/fif.h
@@ -62,7 +65,7 @@ class _Options(ctypes.Structure):
     _fields_ = [("mask_rule", ctypes.c_int32), ("stop_mode", ctypes.c_int32), ("nu", ctypes.c_double),
                 ("max_inner", ctypes.c_int64), ("floor_tau", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("peak_rho", ctypes.c_double), ("window", ctypes.c_void_p), ("window_points", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("precision", ctypes.c_int32)]
 
 
 class LengthPlan(ctypes.Structure):
@@ -111,10 +114,11 @@ class Options:
     gamma: float = 0.0          # > 0: thresholded IMF
     peak_rho: float = 0.1
     window: object = None       # samples of a window shape on [0, 1]; None: the triangle
+    precision: int = 0          # PREC_MIXED (FP64 transforms) or PREC_FP32 (the FP32 lane, no parity claim)
 
     def c(self) -> _Options:
         o = _Options(self.mask_rule, self.stop_mode, self.nu, self.max_inner, self.floor_tau, self.gamma,
-                     self.peak_rho, None, 0, 0)
+                     self.peak_rho, None, 0, self.precision)
         if self.window is not None:
             w = np.ascontiguousarray(np.asarray(self.window, dtype=np.float64).ravel())
             o.window = w.ctypes.data

@@ -13,6 +13,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/fif.h"
@@ -127,6 +128,7 @@ struct fif_plan {
     size_t lds_single = 0, lds_p1 = 0, lds_p2 = 0;
     bool wide = false;              // a length uses tiles above kTileCap elements
     bool pow2 = false;              // every four-step length has radices 2, 4, 8 only
+    bool fp32 = false;              // the FP32 lane (fif_options.precision)
     // device copies (one allocation)
     DevBuf dmeta, dtabs;
     SigDesc* d_sigs = nullptr;
@@ -225,63 +227,54 @@ fif_status set_lds_limits()
             hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
             if (e != hipSuccess && err == hipSuccess) err = e;
         };
-        set((const void*)k_single<MODE_FORWARD, float, float>);
-        set((const void*)k_single<MODE_STEP, float, float>);
-        set((const void*)k_single<MODE_REMAINDER, float, float>);
-        set((const void*)k_single<MODE_FORWARD, double, double>);
-        set((const void*)k_single<MODE_STEP, double, double>);
-        set((const void*)k_single<MODE_REMAINDER, double, double>);
+        // every instantiation the launches use, for both element types
+        auto all = [&](auto tag) {
+            using C = decltype(tag);
+            set((const void*)k_single<MODE_FORWARD, float, float, C>);
+            set((const void*)k_single<MODE_STEP, float, float, C>);
+            set((const void*)k_single<MODE_REMAINDER, float, float, C>);
+            set((const void*)k_single<MODE_FORWARD, double, double, C>);
+            set((const void*)k_single<MODE_STEP, double, double, C>);
+            set((const void*)k_single<MODE_REMAINDER, double, double, C>);
+            auto tiles = [&](auto tile) {
+                constexpr int TL = decltype(tile)::value;
+                set((const void*)k_pass1<MODE_FORWARD, float, false, TL, false, C>);
+                set((const void*)k_pass1<MODE_REMAINDER, float, false, TL, false, C>);
+                set((const void*)k_pass1<MODE_FORWARD, double, false, TL, false, C>);
+                set((const void*)k_pass1<MODE_REMAINDER, double, false, TL, false, C>);
+                set((const void*)k_pass2<MODE_FORWARD, float, float, TL, false, C>);
+                set((const void*)k_pass2<MODE_REMAINDER, float, float, TL, false, C>);
+                set((const void*)k_pass2<MODE_FORWARD, double, double, TL, false, C>);
+                set((const void*)k_pass2<MODE_REMAINDER, double, double, TL, false, C>);
+                auto p2 = [&](auto pow2) {
+                    constexpr bool P2 = decltype(pow2)::value;
+                    set((const void*)k_pass1<MODE_STEP, float, false, TL, P2, C>);
+                    set((const void*)k_pass1<MODE_STEP, float, true, TL, P2, C>);
+                    set((const void*)k_pass1<MODE_STEP, double, false, TL, P2, C>);
+                    set((const void*)k_pass1<MODE_STEP, double, true, TL, P2, C>);
+                    set((const void*)k_pass2<MODE_STEP, float, float, TL, P2, C>);
+                    set((const void*)k_pass2<MODE_STEP, double, double, TL, P2, C>);
+                };
+                p2(std::false_type{});
+                p2(std::true_type{});
+            };
+            tiles(std::integral_constant<int, kTileCap>{});
+            tiles(std::integral_constant<int, kTileCapBig>{});
+            set((const void*)k_scan<kScanBinsPerThread, false, 0, C>);
+            set((const void*)k_scan<kScanBinsPerThread, true, 0, C>);
+            set((const void*)k_scan<kScanBinsPerThread, false, 1, C>);
+            set((const void*)k_scan<kScanBinsPerThread, true, 1, C>);
+            set((const void*)k_scan<kScanBinsPerThread, false, 2, C>);
+            set((const void*)k_scan<kScanBinsPerThread, true, 2, C>);
+        };
+        all(double2{});
+        all(float2{});
+        // sampled window shapes: FP64 transforms only
         set((const void*)k_single<MODE_WINDOW, double, double>);
         set((const void*)k_pass1<MODE_WINDOW, double>);
         set((const void*)k_pass2<MODE_WINDOW, double, double>);
-        set((const void*)k_pass1<MODE_FORWARD, float>);
-        set((const void*)k_pass1<MODE_STEP, float>);
-        set((const void*)k_pass1<MODE_STEP, float, true>);
-        set((const void*)k_pass1<MODE_REMAINDER, float>);
-        set((const void*)k_pass1<MODE_FORWARD, double>);
-        set((const void*)k_pass1<MODE_STEP, double>);
-        set((const void*)k_pass1<MODE_STEP, double, true>);
-        set((const void*)k_pass1<MODE_REMAINDER, double>);
-        set((const void*)k_pass2<MODE_FORWARD, float, float>);
-        set((const void*)k_pass2<MODE_STEP, float, float>);
-        set((const void*)k_pass2<MODE_REMAINDER, float, float>);
-        set((const void*)k_pass2<MODE_FORWARD, double, double>);
-        set((const void*)k_pass2<MODE_STEP, double, double>);
-        set((const void*)k_pass2<MODE_REMAINDER, double, double>);
         set((const void*)k_pass1<MODE_WINDOW, double, false, kTileCapBig>);
         set((const void*)k_pass2<MODE_WINDOW, double, double, kTileCapBig>);
-        set((const void*)k_pass1<MODE_FORWARD, float, false, kTileCapBig>);
-        set((const void*)k_pass1<MODE_STEP, float, false, kTileCapBig>);
-        set((const void*)k_pass1<MODE_STEP, float, true, kTileCapBig>);
-        set((const void*)k_pass1<MODE_REMAINDER, float, false, kTileCapBig>);
-        set((const void*)k_pass1<MODE_FORWARD, double, false, kTileCapBig>);
-        set((const void*)k_pass1<MODE_STEP, double, false, kTileCapBig>);
-        set((const void*)k_pass1<MODE_STEP, double, true, kTileCapBig>);
-        set((const void*)k_pass1<MODE_REMAINDER, double, false, kTileCapBig>);
-        set((const void*)k_pass2<MODE_FORWARD, float, float, kTileCapBig>);
-        set((const void*)k_pass2<MODE_STEP, float, float, kTileCapBig>);
-        set((const void*)k_pass2<MODE_REMAINDER, float, float, kTileCapBig>);
-        set((const void*)k_pass2<MODE_FORWARD, double, double, kTileCapBig>);
-        set((const void*)k_pass2<MODE_STEP, double, double, kTileCapBig>);
-        set((const void*)k_pass2<MODE_REMAINDER, double, double, kTileCapBig>);
-        set((const void*)k_pass1<MODE_STEP, float, false, kTileCap, true>);
-        set((const void*)k_pass1<MODE_STEP, float, true, kTileCap, true>);
-        set((const void*)k_pass1<MODE_STEP, double, false, kTileCap, true>);
-        set((const void*)k_pass1<MODE_STEP, double, true, kTileCap, true>);
-        set((const void*)k_pass1<MODE_STEP, float, false, kTileCapBig, true>);
-        set((const void*)k_pass1<MODE_STEP, float, true, kTileCapBig, true>);
-        set((const void*)k_pass1<MODE_STEP, double, false, kTileCapBig, true>);
-        set((const void*)k_pass1<MODE_STEP, double, true, kTileCapBig, true>);
-        set((const void*)k_pass2<MODE_STEP, float, float, kTileCap, true>);
-        set((const void*)k_pass2<MODE_STEP, double, double, kTileCap, true>);
-        set((const void*)k_pass2<MODE_STEP, float, float, kTileCapBig, true>);
-        set((const void*)k_pass2<MODE_STEP, double, double, kTileCapBig, true>);
-        set((const void*)k_scan<kScanBinsPerThread, false, 0>);
-        set((const void*)k_scan<kScanBinsPerThread, true, 0>);
-        set((const void*)k_scan<kScanBinsPerThread, false, 1>);
-        set((const void*)k_scan<kScanBinsPerThread, true, 1>);
-        set((const void*)k_scan<kScanBinsPerThread, false, 2>);
-        set((const void*)k_scan<kScanBinsPerThread, true, 2>);
     });
     if (err != hipSuccess) return fail(FIF_ERR_DEVICE, "hipFuncSetAttribute: %s", hipGetErrorString(err));
     return FIF_OK;
@@ -313,6 +306,10 @@ fif_status validate_opts(const fif_options& o)
     } else if (o.window_points != 0) {
         return fail(FIF_ERR_INVALID_ARG, "window_points given without window samples");
     }
+    if (o.precision != FIF_PREC_MIXED && o.precision != FIF_PREC_FP32)
+        return fail(FIF_ERR_INVALID_ARG, "precision must be FIF_PREC_MIXED or FIF_PREC_FP32");
+    if (o.precision == FIF_PREC_FP32 && o.window)
+        return fail(FIF_ERR_INVALID_ARG, "the FP32 lane does not take a sampled window shape");
     return FIF_OK;
 }
 
@@ -447,7 +444,7 @@ void fif_options_default(fif_options* opt)
     opt->peak_rho = 0.1;
     opt->window = nullptr;
     opt->window_points = 0;
-    opt->reserved = 0;
+    opt->precision = FIF_PREC_MIXED;
 }
 
 const char* fif_last_error(void) { return g_err.c_str(); }
@@ -582,6 +579,8 @@ fif_status create_plan(fif_plan** out, const int64_t* lengths, int32_t B, int32_
     // signals, work lists, workspace sizes
     int64_t off = 0, spec = 0, inter = 0, inter_max = 0, gscr = 0, resid = 0;
     bool any_odd = false, any_two_pass = false;
+    p->fp32 = p->opt.precision == FIF_PREC_FP32;
+    const size_t esz = p->fp32 ? sizeof(float2) : sizeof(double2);
     int32_t parts = 0, nbig = 0, btiles = 0;
     for (int32_t b = 0; b < B; ++b) {
         const int64_t N = lengths[b];
@@ -628,12 +627,14 @@ fif_status create_plan(fif_plan** out, const int64_t* lengths, int32_t B, int32_
         for (int32_t t = 0; t < d.n_btiles; ++t) p->w_btile.push_back({b, t});
         if (!lp.two_pass) {
             p->w_single.push_back({b, 0});
-            p->lds_single = std::max(p->lds_single, (size_t)N * sizeof(double2));
+            p->lds_single = std::max(p->lds_single, (size_t)N * esz);
         } else {
             for (int32_t t = 0; t < lp.N1 / lp.TC; ++t) p->w_p1.push_back({b, t});
             for (int32_t t = 0; t < lp.N2 / lp.TR; ++t) p->w_p2.push_back({b, t});
-            p->lds_p1 = std::max(p->lds_p1, (size_t)lp.TC * lp.N2 * sizeof(double2));
-            p->lds_p2 = std::max(p->lds_p2, (size_t)lp.TR * lp.N1 * sizeof(double2));
+            p->lds_p1 = std::max(p->lds_p1, (size_t)lp.TC * lp.N2 * esz);
+            // pass 2 also lays the FP64 residual out at a row stride of TR + 1
+            p->lds_p2 = std::max(p->lds_p2, std::max((size_t)lp.TR * lp.N1 * esz,
+                                                     (size_t)(lp.TR + 1) * lp.N1 * sizeof(double)));
             if ((int64_t)lp.TC * lp.N2 > kTileCap || (int64_t)lp.TR * lp.N1 > kTileCap) p->wide = true;
             bool r248 = true;
             for (int i = 0; i < lp.f1.nrad; ++i) r248 = r248 && (lp.f1.rad[i] == 2 || lp.f1.rad[i] == 4 || lp.f1.rad[i] == 8);
@@ -951,42 +952,42 @@ Bound bind(const fif_plan* p, void* ws, double delta, fif_imf_info* info)
 // Four-step passes with the plan's tile size.
 // (The outer steps' passes also have variants without the odd radices, for
 // plans whose lengths need none.)
-template <int MODE, typename T, bool REDO = false>
+template <int MODE, typename T, bool REDO = false, typename C = double2>
 void run_pass1(const fif_plan* p, unsigned grid, hipStream_t s, const StepArgs& A, const T* x)
 {
     constexpr bool STEP = MODE == MODE_STEP;
     if (p->wide) {
         if (STEP && p->pow2)
-            k_pass1<MODE, T, REDO, kTileCapBig, STEP><<<grid, kFftThreads, p->lds_p1, s>>>(A, x);
+            k_pass1<MODE, T, REDO, kTileCapBig, STEP, C><<<grid, kFftThreads, p->lds_p1, s>>>(A, x);
         else
-            k_pass1<MODE, T, REDO, kTileCapBig><<<grid, kFftThreads, p->lds_p1, s>>>(A, x);
+            k_pass1<MODE, T, REDO, kTileCapBig, false, C><<<grid, kFftThreads, p->lds_p1, s>>>(A, x);
     } else {
         if (STEP && p->pow2)
-            k_pass1<MODE, T, REDO, kTileCap, STEP><<<grid, kFftThreads, p->lds_p1, s>>>(A, x);
+            k_pass1<MODE, T, REDO, kTileCap, STEP, C><<<grid, kFftThreads, p->lds_p1, s>>>(A, x);
         else
-            k_pass1<MODE, T, REDO, kTileCap><<<grid, kFftThreads, p->lds_p1, s>>>(A, x);
+            k_pass1<MODE, T, REDO, kTileCap, false, C><<<grid, kFftThreads, p->lds_p1, s>>>(A, x);
     }
 }
-template <int MODE, typename InT, typename OutT>
+template <int MODE, typename InT, typename OutT, typename C = double2>
 void run_pass2(const fif_plan* p, unsigned grid, hipStream_t s, const StepArgs& A, const InT* x, OutT* imfs,
                OutT* rem)
 {
     constexpr bool STEP = MODE == MODE_STEP;
     if (p->wide) {
         if (STEP && p->pow2)
-            k_pass2<MODE, InT, OutT, kTileCapBig, STEP><<<grid, kFftThreads, p->lds_p2, s>>>(A, x, imfs, rem);
+            k_pass2<MODE, InT, OutT, kTileCapBig, STEP, C><<<grid, kFftThreads, p->lds_p2, s>>>(A, x, imfs, rem);
         else
-            k_pass2<MODE, InT, OutT, kTileCapBig><<<grid, kFftThreads, p->lds_p2, s>>>(A, x, imfs, rem);
+            k_pass2<MODE, InT, OutT, kTileCapBig, false, C><<<grid, kFftThreads, p->lds_p2, s>>>(A, x, imfs, rem);
     } else {
         if (STEP && p->pow2)
-            k_pass2<MODE, InT, OutT, kTileCap, STEP><<<grid, kFftThreads, p->lds_p2, s>>>(A, x, imfs, rem);
+            k_pass2<MODE, InT, OutT, kTileCap, STEP, C><<<grid, kFftThreads, p->lds_p2, s>>>(A, x, imfs, rem);
         else
-            k_pass2<MODE, InT, OutT, kTileCap><<<grid, kFftThreads, p->lds_p2, s>>>(A, x, imfs, rem);
+            k_pass2<MODE, InT, OutT, kTileCap, false, C><<<grid, kFftThreads, p->lds_p2, s>>>(A, x, imfs, rem);
     }
 }
 
-template <typename T>
-void launch_init(const fif_plan* p, Bound& b, const T* x, hipStream_t s)
+template <typename T, typename C>
+void launch_init_c(const fif_plan* p, Bound& b, const T* x, hipStream_t s)
 {
     {
         Timed tm(p, "reset", s);
@@ -1001,30 +1002,38 @@ void launch_init(const fif_plan* p, Bound& b, const T* x, hipStream_t s)
     if (!p->w_single.empty()) {
         A.work = p->d_single;
         Timed tm(p, "single_fwd", s);
-        k_single<MODE_FORWARD, T, T><<<(unsigned)p->w_single.size(), kFftThreads, p->lds_single, s>>>(A, x, nullptr,
-                                                                                                     nullptr);
+        k_single<MODE_FORWARD, T, T, C><<<(unsigned)p->w_single.size(), kFftThreads, p->lds_single, s>>>(A, x, nullptr,
+                                                                                                        nullptr);
     }
     if (!p->w_p1.empty()) {
         A.work = p->d_p1;
         {
             Timed tm(p, "pass1_fwd", s);
-            run_pass1<MODE_FORWARD, T>(p, (unsigned)p->w_p1.size(), s, A, x);
+            run_pass1<MODE_FORWARD, T, false, C>(p, (unsigned)p->w_p1.size(), s, A, x);
         }
         A.work = p->d_p2;
         Timed tm(p, "pass2_fwd", s);
-        run_pass2<MODE_FORWARD, T, T>(p, (unsigned)p->w_p2.size(), s, A, x, (T*)nullptr, (T*)nullptr);
+        run_pass2<MODE_FORWARD, T, T, C>(p, (unsigned)p->w_p2.size(), s, A, x, (T*)nullptr, (T*)nullptr);
     }
 }
+template <typename T>
+void launch_init(const fif_plan* p, Bound& b, const T* x, hipStream_t s)
+{
+    if (p->fp32)
+        launch_init_c<T, float2>(p, b, x, s);
+    else
+        launch_init_c<T, double2>(p, b, x, s);
+}
 
-template <bool PRE>
+template <bool PRE, typename C = double2>
 void launch_k_scan(int mode, int n, size_t lds, hipStream_t s, const ScanArgs& S)
 {
     if (mode == 1)
-        k_scan<kScanBinsPerThread, PRE, 1><<<(unsigned)n, kScanThreads, lds, s>>>(S);
+        k_scan<kScanBinsPerThread, PRE, 1, C><<<(unsigned)n, kScanThreads, lds, s>>>(S);
     else if (mode == 2)
-        k_scan<kScanBinsPerThread, PRE, 2><<<(unsigned)n, kScanThreads, lds, s>>>(S);
+        k_scan<kScanBinsPerThread, PRE, 2, C><<<(unsigned)n, kScanThreads, lds, s>>>(S);
     else
-        k_scan<kScanBinsPerThread, PRE, 0><<<(unsigned)n, kScanThreads, lds, s>>>(S);
+        k_scan<kScanBinsPerThread, PRE, 0, C><<<(unsigned)n, kScanThreads, lds, s>>>(S);
 }
 
 // Eigenvalue tables of a sampled window shape for the active signals of one
@@ -1054,6 +1063,7 @@ void launch_window(const fif_plan* p, Bound& b, void* ws, hipStream_t s, const f
 // Search for m of every active signal.  With a proposal model or feature
 // recording the step starts (count combine, stop rules, L) run first, then
 // the features, the network and the proposals, then the searches.
+template <typename C>
 void launch_scan(const fif_plan* p, Bound& b, int t, void* ws, hipStream_t s, const fif_plan::Group& g)
 {
     ScanArgs S = b.sc;
@@ -1064,13 +1074,13 @@ void launch_scan(const fif_plan* p, Bound& b, int t, void* ws, hipStream_t s, co
     const size_t scan_lds = sizeof(float) * kScanBinsPerThread * kScanThreads;
     if (p->opt.mask_rule == 2) {
         Timed tm(p, "peak", s);
-        k_peak<<<(unsigned)(g.s1 - g.s0), 256, 0, s>>>(S, g.s0, p->opt.peak_rho);
+        k_peak<C><<<(unsigned)(g.s1 - g.s0), 256, 0, s>>>(S, g.s0, p->opt.peak_rho);
     }
     if (!split) {
         if (g.ssmall.count) {
             S.list = p->d_scan_small + g.ssmall.begin;
             Timed tm(p, "scan", s);
-            launch_k_scan<false>(p->opt.stop_mode, g.ssmall.count, scan_lds, s, S);
+            launch_k_scan<false, C>(p->opt.stop_mode, g.ssmall.count, scan_lds, s, S);
         }
         if (nb) {
             Timed tm(p, "scan_big", s);
@@ -1122,7 +1132,7 @@ void launch_scan(const fif_plan* p, Bound& b, int t, void* ws, hipStream_t s, co
         if (g.ssmall.count) {
             S.list = p->d_scan_small + g.ssmall.begin;
             Timed tm(p, "scan", s);
-            launch_k_scan<true>(p->opt.stop_mode, g.ssmall.count, scan_lds, s, S);
+            launch_k_scan<true, C>(p->opt.stop_mode, g.ssmall.count, scan_lds, s, S);
         }
         if (nb && p->model) {
             S.list = p->d_scan_big + g.sbig.begin;
@@ -1132,33 +1142,33 @@ void launch_scan(const fif_plan* p, Bound& b, int t, void* ws, hipStream_t s, co
     if (nb) {
         Timed tm(p, "scan_big", s);
         S.list = p->d_scan_big + g.sbig.begin;
-        k_bscan_round<kScanThreads, true><<<nt, kScanThreads, 0, s>>>(S, btile);
-        k_bscan_decide<<<nb, 64 * kDecideGroups, 0, s>>>(S);
+        k_bscan_round<kScanThreads, true, C><<<nt, kScanThreads, 0, s>>>(S, btile);
+        k_bscan_decide<C><<<nb, 64 * kDecideGroups, 0, s>>>(S);
         for (int r = 0; r < kBigRounds; ++r) {
-            k_bscan_round<kScanThreads, false><<<nt, kScanThreads, 0, s>>>(S, btile);
-            k_bscan_decide<<<nb, 64 * kDecideGroups, 0, s>>>(S);
+            k_bscan_round<kScanThreads, false, C><<<nt, kScanThreads, 0, s>>>(S, btile);
+            k_bscan_decide<C><<<nb, 64 * kDecideGroups, 0, s>>>(S);
         }
         k_bscan_final<kScanThreads><<<nb, 64, 0, s>>>(S);
     }
 }
 
-template <typename T>
-void launch_step(const fif_plan* p, Bound& b, int t, const T* x, T* imfs, void* ws, hipStream_t s,
-                 const fif_plan::Group& g)
+template <typename T, typename C>
+void launch_step_c(const fif_plan* p, Bound& b, int t, const T* x, T* imfs, void* ws, hipStream_t s,
+                   const fif_plan::Group& g)
 {
-    launch_scan(p, b, t, ws, s, g);
+    launch_scan<C>(p, b, t, ws, s, g);
     StepArgs A = b.sa;
     A.t = t;
     if (g.single.count) {
         A.work = p->d_single + g.single.begin;
         Timed tm(p, "single_step", s);
-        k_single<MODE_STEP, T, T><<<(unsigned)g.single.count, kFftThreads, p->lds_single, s>>>(A, x, imfs, nullptr);
+        k_single<MODE_STEP, T, T, C><<<(unsigned)g.single.count, kFftThreads, p->lds_single, s>>>(A, x, imfs, nullptr);
     }
     if (g.p1.count) {
         A.work = p->d_p1 + g.p1.begin;
         {
             Timed tm(p, "pass1_step", s);
-            run_pass1<MODE_STEP, T>(p, (unsigned)g.p1.count, s, A, x);
+            run_pass1<MODE_STEP, T, false, C>(p, (unsigned)g.p1.count, s, A, x);
         }
         const unsigned nb = g.big_defer ? (unsigned)g.sbig.count : 0u, nt = (unsigned)g.btile.count;
         if (b.sc.defer && (g.ssmall.count || nb)) {
@@ -1180,7 +1190,7 @@ void launch_step(const fif_plan* p, Bound& b, int t, const T* x, T* imfs, void* 
             V.redo_only = 1;
             if (g.ssmall.count) {
                 V.list = small;
-                launch_k_scan<true>(0, g.ssmall.count, sizeof(float) * kScanBinsPerThread * kScanThreads, s, V);
+                launch_k_scan<true, C>(0, g.ssmall.count, sizeof(float) * kScanBinsPerThread * kScanThreads, s, V);
             }
             if (nb) {
                 // FP64 rounds of the multi-workgroup search for the signals
@@ -1189,16 +1199,16 @@ void launch_step(const fif_plan* p, Bound& b, int t, const T* x, T* imfs, void* 
                 const Work* btile = p->d_btile + g.btile.begin;
                 k_bscan_redo_prep<<<nb, 64, 0, s>>>(V);
                 for (int r = 0; r < kBigRedoRounds; ++r) {
-                    k_bscan_round<kScanThreads, false><<<nt, kScanThreads, 0, s>>>(V, btile);
-                    k_bscan_decide<<<nb, 64 * kDecideGroups, 0, s>>>(V);
+                    k_bscan_round<kScanThreads, false, C><<<nt, kScanThreads, 0, s>>>(V, btile);
+                    k_bscan_decide<C><<<nb, 64 * kDecideGroups, 0, s>>>(V);
                 }
                 k_bscan_final<kScanThreads><<<nb, 64, 0, s>>>(V);
             }
-            run_pass1<MODE_STEP, T, true>(p, (unsigned)g.p1.count, s, A, x);
+            run_pass1<MODE_STEP, T, true, C>(p, (unsigned)g.p1.count, s, A, x);
         }
         A.work = p->d_p2 + g.p2.begin;
         Timed tm(p, "pass2_step", s);
-        run_pass2<MODE_STEP, T, T>(p, (unsigned)g.p2.count, s, A, x, imfs, (T*)nullptr);
+        run_pass2<MODE_STEP, T, T, C>(p, (unsigned)g.p2.count, s, A, x, imfs, (T*)nullptr);
     }
     if (g.count.count) {
         Timed tm(p, "count_resid", s);
@@ -1206,10 +1216,19 @@ void launch_step(const fif_plan* p, Bound& b, int t, const T* x, T* imfs, void* 
                                                                        A.parts, A.st);
     }
 }
-
 template <typename T>
-void launch_final(const fif_plan* p, Bound& b, const T* x, T* rem, int32_t* n_imfs, int32_t* sig_status,
-                  fif_imf_info* info, hipStream_t s)
+void launch_step(const fif_plan* p, Bound& b, int t, const T* x, T* imfs, void* ws, hipStream_t s,
+                 const fif_plan::Group& g)
+{
+    if (p->fp32)
+        launch_step_c<T, float2>(p, b, t, x, imfs, ws, s, g);
+    else
+        launch_step_c<T, double2>(p, b, t, x, imfs, ws, s, g);
+}
+
+template <typename T, typename C>
+void launch_final_c(const fif_plan* p, Bound& b, const T* x, T* rem, int32_t* n_imfs, int32_t* sig_status,
+                    fif_imf_info* info, hipStream_t s)
 {
     {
         Timed tm(p, "finalize", s);
@@ -1219,19 +1238,28 @@ void launch_final(const fif_plan* p, Bound& b, const T* x, T* rem, int32_t* n_im
     if (!p->w_single.empty()) {
         A.work = p->d_single;
         Timed tm(p, "single_rem", s);
-        k_single<MODE_REMAINDER, T, T><<<(unsigned)p->w_single.size(), kFftThreads, p->lds_single, s>>>(A, x, nullptr,
-                                                                                                       rem);
+        k_single<MODE_REMAINDER, T, T, C><<<(unsigned)p->w_single.size(), kFftThreads, p->lds_single, s>>>(A, x, nullptr,
+                                                                                                          rem);
     }
     if (!p->w_p1.empty()) {
         A.work = p->d_p1;
         {
             Timed tm(p, "pass1_rem", s);
-            run_pass1<MODE_REMAINDER, T>(p, (unsigned)p->w_p1.size(), s, A, x);
+            run_pass1<MODE_REMAINDER, T, false, C>(p, (unsigned)p->w_p1.size(), s, A, x);
         }
         A.work = p->d_p2;
         Timed tm(p, "pass2_rem", s);
-        run_pass2<MODE_REMAINDER, T, T>(p, (unsigned)p->w_p2.size(), s, A, x, (T*)nullptr, rem);
+        run_pass2<MODE_REMAINDER, T, T, C>(p, (unsigned)p->w_p2.size(), s, A, x, (T*)nullptr, rem);
     }
+}
+template <typename T>
+void launch_final(const fif_plan* p, Bound& b, const T* x, T* rem, int32_t* n_imfs, int32_t* sig_status,
+                  fif_imf_info* info, hipStream_t s)
+{
+    if (p->fp32)
+        launch_final_c<T, float2>(p, b, x, rem, n_imfs, sig_status, info, s);
+    else
+        launch_final_c<T, double2>(p, b, x, rem, n_imfs, sig_status, info, s);
 }
 
 // Streams and events of the signal groups (created once per plan).
@@ -1482,7 +1510,7 @@ struct SingleCache {
         SigState* host_state = nullptr;
     };
     std::map<std::tuple<int, int64_t, int32_t, int32_t, double, int64_t, double, int32_t, double, double,
-                        std::vector<double>>,
+                        std::vector<double>, int32_t>,
              Entry>
         map;
     ~SingleCache() { clear(); }
@@ -1529,7 +1557,7 @@ fif_status single(const T* x, int64_t N, fif_window window, double delta, int32_
     std::vector<double> wkey;
     if (opt.window) wkey.assign(opt.window, opt.window + opt.window_points);
     auto key = std::make_tuple(dev, N, max_imfs, opt.mask_rule, opt.nu, opt.max_inner, opt.floor_tau, opt.stop_mode,
-                               opt.gamma, opt.peak_rho, wkey);
+                               opt.gamma, opt.peak_rho, wkey, opt.precision);
     auto it = C.map.find(key);
     if (it == C.map.end()) {
         SingleCache::Entry e;
@@ -1694,7 +1722,8 @@ fif_status fif_plan_create_tuned(fif_plan** out, const int64_t* lengths, int32_t
     fif_status st = validate_opts(opt);
     if (st) return st;
     const char* path = tune_cache ? tune_cache : getenv("FIF_TUNE_CACHE");
-    const std::string key = device_key();
+    // the FP32 lane's kernels differ: its choices are cached apart
+    const std::string key = device_key() + (opt.precision == FIF_PREC_FP32 ? "/fp32" : "");
     ChoiceMap chosen;
     for (int32_t b = 0; b < B; ++b) {
         const int64_t N = lengths[b];
@@ -1782,6 +1811,7 @@ fif_status fif_plan_set_proposal(fif_plan* plan, fif_model* model)
     if (!plan) return fail(FIF_ERR_INVALID_ARG, "plan is null");
     if (model && model_device(model) != plan->device)
         return fail(FIF_ERR_INVALID_ARG, "model and plan live on different devices");
+    if (model && plan->fp32) return fail(FIF_ERR_INVALID_ARG, "the FP32 lane takes no proposal network");
     plan->model = model;
     return FIF_OK;
 }
@@ -1791,6 +1821,7 @@ fif_status fif_plan_record_features(fif_plan* plan, uint16_t* feats)
     g_err.clear();
     if (!plan) return fail(FIF_ERR_INVALID_ARG, "plan is null");
     if (((uintptr_t)feats) % 16) return fail(FIF_ERR_INVALID_ARG, "feats must be 16-byte aligned");
+    if (feats && plan->fp32) return fail(FIF_ERR_INVALID_ARG, "the FP32 lane records no features");
     plan->rec = feats;
     return FIF_OK;
 }

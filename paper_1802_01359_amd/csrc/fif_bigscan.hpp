@@ -150,7 +150,7 @@ __device__ __forceinline__ void wave_reduce_scatter(float* v, int lane)
     }
 }
 
-template <int T, int BPT>
+template <int T, int BPT, typename C>
 __device__ __forceinline__ void bscan_tile_sums(const ScanArgs& A, const SigDesc& d, const LenPlan& lp,
                                                 const BigScan* G, int tile, double* out, float* shf,
                                                 double* shd)
@@ -160,7 +160,7 @@ __device__ __forceinline__ void bscan_tile_sums(const ScanArgs& A, const SigDesc
     const int j0 = 1 + tile * kBigTile;
     const int ph = G->phase;
     const int nc = G->ncand;
-    const double2* R = ((A.t & 1) ? A.spec1 : A.spec0) + d.spec_off;
+    const auto R = spec_view<C>((A.t & 1) ? A.spec1 : A.spec0, d.spec_off);
     if (ph < 2) {
         const float* tau = A.gscr + d.gs_off;
         const float* av = tau + nh;
@@ -556,7 +556,7 @@ __device__ __forceinline__ void bscan_decide(const ScanArgs& A, int s, const Sig
 }
 
 // One candidate round over one tile (first round: also fill the scratch).
-template <int T, bool SWEEP>
+template <int T, bool SWEEP, typename C = double2>
 __global__ __launch_bounds__(T) void k_bscan_round(ScanArgs A, const Work* __restrict__ work)
 {
     constexpr int BPT = kBigTile / T;
@@ -574,7 +574,7 @@ __global__ __launch_bounds__(T) void k_bscan_round(ScanArgs A, const Work* __res
         float* tau = A.gscr + d.gs_off;
         float* av = tau + nh;
         float* bv = av + nh;
-        const double2* R = ((A.t & 1) ? A.spec1 : A.spec0) + d.spec_off;
+        const auto R = spec_view<C>((A.t & 1) ? A.spec1 : A.spec0, d.spec_off);
         const Lam lw = make_lam(lp, A.dtab, G->L, A.lam ? A.lam + d.spec_off : nullptr);
         // position -> bin table of this length, read once (null: bin order)
         const int32_t* btab = lp.spec_perm ? A.itab + lp.bin_off : nullptr;
@@ -618,13 +618,14 @@ __global__ __launch_bounds__(T) void k_bscan_round(ScanArgs A, const Work* __res
         if (threadIdx.x == 0) A.bqmax[d.bt_off + w.tile] = qmx;
         // each thread reads back only its own bins below
     }
-    bscan_tile_sums<T, BPT>(A, d, lp, G, w.tile, shv, shf, shd);
+    bscan_tile_sums<T, BPT, C>(A, d, lp, G, w.tile, shv, shf, shd);
     double* P = A.bpart + ((int64_t)d.bt_off + w.tile) * 2 * kBigCand;
     const int nc = G->ncand;
     if (threadIdx.x < 2 * nc) P[threadIdx.x] = shv[threadIdx.x];
 }
 
 // After a round: tile totals in tile order, then the next candidates.
+template <typename C = double2>
 __global__ __launch_bounds__(64 * kDecideGroups) void k_bscan_decide(ScanArgs A)
 {
     __shared__ double part[64 * kDecideGroups];
@@ -651,7 +652,7 @@ __global__ __launch_bounds__(64 * kDecideGroups) void k_bscan_decide(ScanArgs A)
             G->qthr = A.stop_mode == 0 ? kSdNoise * q : 0.0;
             G->mt = 0;
             if (A.stop_mode != 0) {
-                const double2 r0 = (((A.t & 1) ? A.spec1 : A.spec0) + d.spec_off)[0];
+                const double2 r0 = spec_view<C>((A.t & 1) ? A.spec1 : A.spec0, d.spec_off)[0];
                 const int64_t n0 = apriori_n0(fmax(q, r0.x * r0.x + r0.y * r0.y), G->L, d.N, A.delta);
                 if (A.stop_mode == 1) {
                     G->mt = min(n0, A.max_inner) + 1;     // as a count c = m + 1

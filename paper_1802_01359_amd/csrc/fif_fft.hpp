@@ -20,6 +20,9 @@
 
 namespace fif {
 
+// Complex arithmetic for the two element types of the transforms: double2
+// (FP64 transforms) and float2 (the FP32 lane).  Mixed-precision constants
+// (the radix-8 and odd-radix cosines) are rounded to the element type.
 __device__ __forceinline__ double2 cmul(double2 a, double2 b)
 {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -27,12 +30,35 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b)
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b)
+{
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cscale(float2 a, double s)
+{
+    const float f = (float)s;
+    return make_float2(a.x * f, a.y * f);
+}
 // multiply by s*i, s = +1 (inverse direction) or -1 (forward direction)
 template <bool INV>
 __device__ __forceinline__ double2 mul_si(double2 a)
 {
     return INV ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
 }
+template <bool INV>
+__device__ __forceinline__ float2 mul_si(float2 a)
+{
+    return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+// conversions between the element types and FP64
+template <typename C> __device__ __forceinline__ C to_c(double2 v);
+template <> __device__ __forceinline__ double2 to_c<double2>(double2 v) { return v; }
+template <> __device__ __forceinline__ float2 to_c<float2>(double2 v) { return make_float2((float)v.x, (float)v.y); }
+__device__ __forceinline__ double2 to_d(double2 v) { return v; }
+__device__ __forceinline__ double2 to_d(float2 v) { return make_double2((double)v.x, (double)v.y); }
+template <typename C> __device__ __forceinline__ C czero() { return to_c<C>(make_double2(0.0, 0.0)); }
 
 // cos / sin of 2 pi p / R, p <= (R-1)/2, for the odd radices (correctly
 // rounded literals)
@@ -57,19 +83,21 @@ __device__ __forceinline__ constexpr double odd_sin(int p)
 template <int R, bool INV> struct Dft;
 
 template <bool INV> struct Dft<2, INV> {
-    __device__ __forceinline__ static void run(double2* a)
+    template <typename C>
+    __device__ __forceinline__ static void run(C* a)
     {
-        double2 t = a[0];
+        C t = a[0];
         a[0] = cadd(t, a[1]);
         a[1] = csub(t, a[1]);
     }
 };
 
 template <bool INV> struct Dft<4, INV> {
-    __device__ __forceinline__ static void run(double2* a)
+    template <typename C>
+    __device__ __forceinline__ static void run(C* a)
     {
-        double2 s02 = cadd(a[0], a[2]), d02 = csub(a[0], a[2]);
-        double2 s13 = cadd(a[1], a[3]), d13 = mul_si<INV>(csub(a[1], a[3]));
+        C s02 = cadd(a[0], a[2]), d02 = csub(a[0], a[2]);
+        C s13 = cadd(a[1], a[3]), d13 = mul_si<INV>(csub(a[1], a[3]));
         a[0] = cadd(s02, s13);
         a[2] = csub(s02, s13);
         a[1] = cadd(d02, d13);
@@ -78,17 +106,18 @@ template <bool INV> struct Dft<4, INV> {
 };
 
 template <bool INV> struct Dft<8, INV> {
-    __device__ __forceinline__ static void run(double2* a)
+    template <typename C>
+    __device__ __forceinline__ static void run(C* a)
     {
         constexpr double h = 0.7071067811865476;
-        double2 e[4] = {a[0], a[2], a[4], a[6]};
-        double2 o[4] = {a[1], a[3], a[5], a[7]};
+        C e[4] = {a[0], a[2], a[4], a[6]};
+        C o[4] = {a[1], a[3], a[5], a[7]};
         Dft<4, INV>::run(e);
         Dft<4, INV>::run(o);
         // w8^1 = h (1 + s i), w8^2 = s i, w8^3 = h (-1 + s i)
-        double2 o1 = cscale(cadd(o[1], mul_si<INV>(o[1])), h);
-        double2 o2 = mul_si<INV>(o[2]);
-        double2 o3 = cscale(csub(mul_si<INV>(o[3]), o[3]), h);
+        C o1 = cscale(cadd(o[1], mul_si<INV>(o[1])), h);
+        C o2 = mul_si<INV>(o[2]);
+        C o3 = cscale(csub(mul_si<INV>(o[3]), o[3]), h);
         a[0] = cadd(e[0], o[0]);
         a[4] = csub(e[0], o[0]);
         a[1] = cadd(e[1], o1);
@@ -102,24 +131,25 @@ template <bool INV> struct Dft<8, INV> {
 
 // odd R: pair inputs q and R-q; X_k and X_{R-k} share the cosine part
 template <int R, bool INV> struct DftOdd {
-    __device__ __forceinline__ static void run(double2* a)
+    template <typename C>
+    __device__ __forceinline__ static void run(C* a)
     {
         constexpr int H = (R - 1) / 2;
-        double2 t[H], u[H];
+        C t[H], u[H];
 #pragma unroll
         for (int q = 1; q <= H; ++q) {
             t[q - 1] = cadd(a[q], a[R - q]);
             u[q - 1] = csub(a[q], a[R - q]);
         }
-        double2 x0 = a[0];
+        C x0 = a[0];
 #pragma unroll
         for (int q = 0; q < H; ++q) x0 = cadd(x0, t[q]);
-        double2 out[R];
+        C out[R];
         out[0] = x0;
 #pragma unroll
         for (int k = 1; k <= H; ++k) {
-            double2 re = a[0];
-            double2 im = make_double2(0.0, 0.0);
+            C re = a[0];
+            C im = czero<C>();
 #pragma unroll
             for (int q = 1; q <= H; ++q) {
                 const int p = (q * k) % R;
@@ -129,7 +159,7 @@ template <int R, bool INV> struct DftOdd {
                 re = cadd(re, cscale(t[q - 1], cs));
                 im = cadd(im, cscale(u[q - 1], sn));
             }
-            double2 sim = mul_si<INV>(im);
+            C sim = mul_si<INV>(im);
             out[k] = cadd(re, sim);
             out[R - k] = csub(re, sim);
         }
@@ -173,16 +203,17 @@ __device__ __forceinline__ int fdivmod(int x, FastDiv f, int& rem)
     return q;
 }
 
-// One Stockham pass over `batch` interleaved sequences, CAP >= n * batch.
-template <int R, bool INV, int CAP>
-__device__ __forceinline__ void fft_pass(double2* __restrict__ buf, int n, int batch, int ns,
+// One Stockham pass over `batch` interleaved sequences, CAP >= n * batch,
+// elements of type C (double2 or float2; the twiddle tables are FP64).
+template <int R, bool INV, int CAP, typename C>
+__device__ __forceinline__ void fft_pass(C* __restrict__ buf, int n, int batch, int ns,
                                          const double2* __restrict__ tw)
 {
     constexpr int Q = (CAP / R + kFftThreads - 1) / kFftThreads;
     const int nb = n / R;
     const int items = nb * batch;
     const FastDiv fb = fastdiv(batch), fn = fastdiv(ns);
-    double2 v[Q][R];
+    C v[Q][R];
     int jq[Q], cq[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -205,9 +236,9 @@ __device__ __forceinline__ void fft_pass(double2* __restrict__ buf, int n, int b
             int k;
             const int jd = fdivmod(j, fn, k);
             if (ns > 1) {
-                double2 w = tw[k];
+                C w = to_c<C>(tw[k]);
                 if (INV) w.y = -w.y;
-                double2 wr = w;
+                C wr = w;
 #pragma unroll
                 for (int r = 1; r < R; ++r) {
                     v[q][r] = cmul(v[q][r], wr);
@@ -227,8 +258,8 @@ __device__ __forceinline__ void fft_pass(double2* __restrict__ buf, int n, int b
 // (f.n * batch <= CAP).  Caller must __syncthreads() after filling buf.
 // P2: the plan has radices 2, 4 and 8 only (kernels without the odd-radix
 // passes need fewer registers).
-template <bool INV, int CAP, bool P2 = false>
-__device__ __forceinline__ void lds_fft(double2* __restrict__ buf, const SubFft& f, int batch,
+template <bool INV, int CAP, bool P2 = false, typename C>
+__device__ __forceinline__ void lds_fft(C* __restrict__ buf, const SubFft& f, int batch,
                                         const double2* __restrict__ twbase)
 {
     const double2* tw = twbase + f.tw_off;
@@ -237,18 +268,18 @@ __device__ __forceinline__ void lds_fft(double2* __restrict__ buf, const SubFft&
         const int R = f.rad[p];
         if (P2) {
             switch (R) {
-            case 2: fft_pass<2, INV, CAP>(buf, f.n, batch, ns, tw); break;
-            case 4: fft_pass<4, INV, CAP>(buf, f.n, batch, ns, tw); break;
-            default: fft_pass<8, INV, CAP>(buf, f.n, batch, ns, tw); break;
+            case 2: fft_pass<2, INV, CAP, C>(buf, f.n, batch, ns, tw); break;
+            case 4: fft_pass<4, INV, CAP, C>(buf, f.n, batch, ns, tw); break;
+            default: fft_pass<8, INV, CAP, C>(buf, f.n, batch, ns, tw); break;
             }
         } else {
             switch (R) {
-            case 2: fft_pass<2, INV, CAP>(buf, f.n, batch, ns, tw); break;
-            case 3: fft_pass<3, INV, CAP>(buf, f.n, batch, ns, tw); break;
-            case 4: fft_pass<4, INV, CAP>(buf, f.n, batch, ns, tw); break;
-            case 5: fft_pass<5, INV, CAP>(buf, f.n, batch, ns, tw); break;
-            case 7: fft_pass<7, INV, CAP>(buf, f.n, batch, ns, tw); break;
-            default: fft_pass<8, INV, CAP>(buf, f.n, batch, ns, tw); break;
+            case 2: fft_pass<2, INV, CAP, C>(buf, f.n, batch, ns, tw); break;
+            case 3: fft_pass<3, INV, CAP, C>(buf, f.n, batch, ns, tw); break;
+            case 4: fft_pass<4, INV, CAP, C>(buf, f.n, batch, ns, tw); break;
+            case 5: fft_pass<5, INV, CAP, C>(buf, f.n, batch, ns, tw); break;
+            case 7: fft_pass<7, INV, CAP, C>(buf, f.n, batch, ns, tw); break;
+            default: fft_pass<8, INV, CAP, C>(buf, f.n, batch, ns, tw); break;
             }
         }
         tw += ns;

@@ -592,6 +592,19 @@ struct StepArgs {
 // Spectrum buffer index read by outer step t.
 __device__ __forceinline__ double2* spec_in(const StepArgs& A, int buf) { return buf ? A.spec1 : A.spec0; }
 
+// Read-only view of a stored spectrum (elements of type C) that hands out
+// FP64 bins, for the searches.
+template <typename C>
+struct SpecView {
+    const C* p;
+    __device__ __forceinline__ double2 operator[](int64_t i) const { return to_d(p[i]); }
+};
+template <typename C>
+__device__ __forceinline__ SpecView<C> spec_view(const double2* base, int64_t off)
+{
+    return SpecView<C>{reinterpret_cast<const C*>(base) + off};
+}
+
 // Element z_k of the inverse-transform input for k in [0, N): bin
 // j = min(k, N-k) of the current residual spectrum (conjugated for k > N/2)
 // times (g_j + i (1 - g_j)) / N.
@@ -608,11 +621,14 @@ __device__ __forceinline__ double2 step_input(double2 v, bool mirror, double g, 
 // and nothing else.  STEP: apply, inverse transform, IMF row t, run summary,
 // min and max of the residual, next spectrum.  REMAINDER: inverse transform
 // of the final spectrum, imaginary part only.
-template <int MODE, typename InT, typename OutT>
+// C: element type of the transform and of the stored spectra (double2;
+// float2 in the FP32 lane, whose lambda, powers and sums stay FP64).
+template <int MODE, typename InT, typename OutT, typename C = double2>
 __global__ __launch_bounds__(kFftThreads) void k_single(StepArgs A, const InT* __restrict__ x,
                                                         OutT* __restrict__ imfs, OutT* __restrict__ rem)
 {
-    extern __shared__ double2 lds[];
+    extern __shared__ double2 lds_raw[];
+    C* lds = reinterpret_cast<C*>(lds_raw);
     __shared__ RunState sh[kFftThreads / 64];
     __shared__ double shd[2 * (kFftThreads / 64)];
     const Work w = A.work[blockIdx.x];
@@ -624,7 +640,7 @@ __global__ __launch_bounds__(kFftThreads) void k_single(StepArgs A, const InT* _
 
     if (fwd_mode(MODE)) {
         if (MODE == MODE_WINDOW && !S->active) return;
-        for (int k = threadIdx.x; k < N; k += kFftThreads) lds[k] = make_double2((double)x[d.off + k], 0.0);
+        for (int k = threadIdx.x; k < N; k += kFftThreads) lds[k] = to_c<C>(make_double2((double)x[d.off + k], 0.0));
         __syncthreads();
         lds_fft<false, kFftCap>(lds, lp.f1, 1, A.ctab);
         if (MODE == MODE_WINDOW) {
@@ -633,7 +649,7 @@ __global__ __launch_bounds__(kFftThreads) void k_single(StepArgs A, const InT* _
             for (int k = threadIdx.x; k <= nh; k += kFftThreads) lt[k] = window_lambda(k, lds[k].x, inv);
             return;
         }
-        double2* out = A.spec0 + d.spec_off;
+        C* out = reinterpret_cast<C*>(A.spec0) + d.spec_off;
         for (int k = threadIdx.x; k <= nh; k += kFftThreads) out[k] = lds[k];
         return;
     }
@@ -647,18 +663,18 @@ __global__ __launch_bounds__(kFftThreads) void k_single(StepArgs A, const InT* _
         return;
     }
     const int buf = (MODE == MODE_STEP) ? (A.t & 1) : S->final_buf;
-    const double2* Rin = spec_in(A, buf) + d.spec_off;
-    double2* Rout = spec_in(A, buf ^ 1) + d.spec_off;
+    const C* Rin = reinterpret_cast<const C*>(spec_in(A, buf)) + d.spec_off;
+    C* Rout = reinterpret_cast<C*>(spec_in(A, buf ^ 1)) + d.spec_off;
     const double invN = 1.0 / (double)N;
     const int64_t L = S->L, m = S->m;
     const Lam lw = make_lam(lp, A.dtab, L > 0 ? L : 1, A.lam ? A.lam + d.spec_off : nullptr);
     for (int j = threadIdx.x; j <= nh; j += kFftThreads) {
-        const double2 v = Rin[j];
+        const double2 v = to_d(Rin[j]);
         double g = 0.0;
         if (MODE == MODE_STEP) g = gain_th(gain_pow(lambda_at(j, lw), m), A.gamma);
-        lds[j] = step_input(v, false, g, invN);
-        if (j != 0 && 2 * j != N) lds[N - j] = step_input(v, true, g, invN);
-        if (MODE == MODE_STEP) Rout[j] = cscale(v, 1.0 - g);
+        lds[j] = to_c<C>(step_input(v, false, g, invN));
+        if (j != 0 && 2 * j != N) lds[N - j] = to_c<C>(step_input(v, true, g, invN));
+        if (MODE == MODE_STEP) Rout[j] = to_c<C>(cscale(v, 1.0 - g));
     }
     __syncthreads();
     lds_fft<true, kFftCap>(lds, lp.f1, 1, A.ctab);
@@ -820,10 +836,11 @@ __global__ void k_fill_specmap(const LenPlan* __restrict__ lpp, int32_t* __restr
 // TILE: largest tile of the plan's lengths (kTileCap, or kTileCapBig when a
 // length needs the wide tiles); it sizes the register staging and the LDS
 // passes.
-template <int MODE, typename InT, bool REDO = false, int TILE = kTileCap, bool P2 = false>
+template <int MODE, typename InT, bool REDO = false, int TILE = kTileCap, bool P2 = false, typename C = double2>
 __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __restrict__ x)
 {
-    extern __shared__ double2 lds[];
+    extern __shared__ double2 lds_raw[];
+    C* lds = reinterpret_cast<C*>(lds_raw);
     const Work w = A.work[blockIdx.x];
     const SigDesc d = A.sigs[w.sig];
     const LenPlan& lp = A.lens[d.len_id];
@@ -840,12 +857,12 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
         for (int f = threadIdx.x; f < total; f += kFftThreads) {
             int s;
             const int r = fdivmod(f, ftc, s);
-            lds[f] = make_double2((double)x[d.off + pass1_col(pr, w.tile, s) + (int64_t)N1 * r], 0.0);
+            lds[f] = to_c<C>(make_double2((double)x[d.off + pass1_col(pr, w.tile, s) + (int64_t)N1 * r], 0.0));
         }
     } else {
         const int buf = (MODE == MODE_STEP) ? (A.t & 1) : S->final_buf;
-        const double2* Rin = spec_in(A, buf) + d.spec_off;
-        double2* Rout = spec_in(A, buf ^ 1) + d.spec_off;
+        const C* Rin = reinterpret_cast<const C*>(spec_in(A, buf)) + d.spec_off;
+        C* Rout = reinterpret_cast<C*>(spec_in(A, buf ^ 1)) + d.spec_off;
         const double invN = 1.0 / (double)N;
         const int64_t L = S->L, m = S->m;
         const Lam lw = make_lam(lp, A.dtab, L > 0 ? L : 1, A.lam ? A.lam + d.spec_off : nullptr);
@@ -855,7 +872,7 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
             // the tile's bins are one contiguous run (tile order, see
             // spec_pos); all of a thread's loads are issued first
             constexpr int PQ = TILE / 2 / kFftThreads + 1;
-            double2 vv[PQ];
+            C vv[PQ];
             // deferred FP64 check of m: this tile's part of the stop-test sums,
             // over the bins above the scan's noise floor
             const bool chk = MODE == MODE_STEP && S->chk;
@@ -865,7 +882,7 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
 #pragma unroll
             for (int q = 0; q < PQ; ++q) {
                 const int f = threadIdx.x + q * kFftThreads;
-                vv[q] = make_double2(0.0, 0.0);
+                vv[q] = czero<C>();
                 if (f < owners)
                     vv[q] = Rin[pbase + f];
                 else if (f == owners && w.tile == 0)
@@ -885,7 +902,7 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
                 const int c = pass1_col(pr, w.tile, s);
                 const int64_t k = c + (int64_t)N1 * r;
                 const int64_t pk = (f < owners) ? pbase + f : (N >> 1);
-                const double2 v = vv[q];
+                const double2 v = to_d(vv[q]);
                 double g = 0.0;
                 if (MODE == MODE_STEP) {
                     // (1-lambda)^m built from (1-lambda)^(m-2) so that the
@@ -912,7 +929,7 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
                     }
                     g = gain_th(g, A.gamma);
                 }
-                lds[r * TC + s] = step_input(v, false, g, invN);
+                lds[r * TC + s] = to_c<C>(step_input(v, false, g, invN));
                 if (f < owners) {
                     int ms, mr;
                     if (c == 0) {
@@ -922,9 +939,9 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
                         ms = (s == h && w.tile == 0) ? s : (s < h ? s + h : s - h);
                         mr = N2 - 1 - r;
                     }
-                    if (!(c == 0 && r == 0)) lds[mr * TC + ms] = step_input(v, true, g, invN);
+                    if (!(c == 0 && r == 0)) lds[mr * TC + ms] = to_c<C>(step_input(v, true, g, invN));
                 }
-                if (MODE == MODE_STEP) Rout[pk] = cscale(v, 1.0 - g);
+                if (MODE == MODE_STEP) Rout[pk] = to_c<C>(cscale(v, 1.0 - g));
             }
             if (chk) {
                 __shared__ double shc[4 * (kFftThreads / 64)];
@@ -947,7 +964,7 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
                 const int64_t k = pass1_col(pr, w.tile, s) + (int64_t)N1 * r;
                 const bool mirror = k > nh;
                 const int64_t j = mirror ? N - k : k;
-                const double2 v = Rin[j];
+                const double2 v = to_d(Rin[j]);
                 double g = 0.0;
                 if (MODE == MODE_STEP) {
                     const double lam = lambda_at(j, lw);
@@ -977,8 +994,8 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
                     }
                     g = gain_th(g, A.gamma);
                 }
-                lds[f] = step_input(v, mirror, g, invN);
-                if (MODE == MODE_STEP && !mirror) Rout[j] = cscale(v, 1.0 - g);
+                lds[f] = to_c<C>(step_input(v, mirror, g, invN));
+                if (MODE == MODE_STEP && !mirror) Rout[j] = to_c<C>(cscale(v, 1.0 - g));
             }
             if (chk) {
                 __shared__ double shu[4 * (kFftThreads / 64)];
@@ -995,17 +1012,17 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
         lds_fft<false, TILE, P2>(lds, lp.f1, TC, A.ctab);
     else
         lds_fft<true, TILE, P2>(lds, lp.f1, TC, A.ctab);
-    double2* Y = A.inter + d.inter_off;
+    C* Y = reinterpret_cast<C*>(A.inter) + d.inter_off;
     for (int f = threadIdx.x; f < total; f += kFftThreads) {
         int s;
         const int rp = fdivmod(f, ftc, s);
         const int c = pass1_col(pr, w.tile, s);
         const int64_t a = (int64_t)rp * c;
-        double2 v = lds[f];
+        C v = lds[f];
         if (a != 0) {
             const double2 tw = fwd_mode(MODE) ? big_twiddle<false>(pr, A.ctab, a)
                                               : big_twiddle<true>(pr, A.ctab, a);
-            v = cmul(v, tw);
+            v = cmul(v, to_c<C>(tw));
         }
         Y[(int64_t)w.tile * total + f] = v;
     }
@@ -1017,11 +1034,12 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
 // (length N1); output element N2 * c' + r'.  STEP: IMF, one run summary per
 // c' (TR consecutive samples) and the tile's min/max; FORWARD: half
 // spectrum; REMAINDER: y.
-template <int MODE, typename InT, typename OutT, int TILE = kTileCap, bool P2 = false>
+template <int MODE, typename InT, typename OutT, int TILE = kTileCap, bool P2 = false, typename C = double2>
 __global__ __launch_bounds__(kFftThreads) void k_pass2(StepArgs A, const InT* __restrict__ x,
                                                        OutT* __restrict__ imfs, OutT* __restrict__ rem)
 {
-    extern __shared__ double2 lds[];
+    extern __shared__ double2 lds_raw[];
+    C* lds = reinterpret_cast<C*>(lds_raw);
     __shared__ double shd[2 * (kFftThreads / 64)];
     const Work w = A.work[blockIdx.x];
     const SigDesc d = A.sigs[w.sig];
@@ -1053,7 +1071,7 @@ __global__ __launch_bounds__(kFftThreads) void k_pass2(StepArgs A, const InT* __
         }
         return;
     }
-    const double2* Y = A.inter + d.inter_off;
+    const C* Y = reinterpret_cast<const C*>(A.inter) + d.inter_off;
     {
         // e = (t * TC + s) * TR + rl: consecutive lanes take consecutive
         // rows of one column, so the LDS stores below are conflict free;
@@ -1062,11 +1080,11 @@ __global__ __launch_bounds__(kFftThreads) void k_pass2(StepArgs A, const InT* __
         const FastDiv ftc = fastdiv(TC);
         const int64_t blk = (int64_t)TC * N2;
         constexpr int GQ = TILE / kFftThreads;
-        double2 yv[GQ];
+        C yv[GQ];
 #pragma unroll
         for (int q = 0; q < GQ; ++q) {
             const int e = threadIdx.x + q * kFftThreads;
-            yv[q] = make_double2(0.0, 0.0);
+            yv[q] = czero<C>();
             if (e < total) {
                 int s, rl;
                 const int u = fdivmod(e, ftr, rl);
@@ -1103,7 +1121,7 @@ __global__ __launch_bounds__(kFftThreads) void k_pass2(StepArgs A, const InT* __
         return;
     }
     if (MODE == MODE_FORWARD) {
-        double2* out = A.spec0 + d.spec_off;
+        C* out = reinterpret_cast<C*>(A.spec0) + d.spec_off;
         const int64_t nh = N / 2;
         for (int f = threadIdx.x; f < total; f += kFftThreads) {
             int rl;
@@ -1133,7 +1151,7 @@ __global__ __launch_bounds__(kFftThreads) void k_pass2(StepArgs A, const InT* __
         if (f < total) {
             int rl;
             const int cp = fdivmod(f, ftr, rl);
-            const double2 v = lds[f];
+            const C v = lds[f];
             row[(int64_t)N2 * cp + r0 + rl] = (OutT)v.x;
             yv[q] = v.y;
         }
@@ -1296,6 +1314,7 @@ __device__ __forceinline__ void scan_prologue(const ScanArgs& A, int s, const Si
 // Spectral-peak bin of every active signal s0 + b (mask rule 2): the highest
 // bin f in [1, N/2] with |R_f|^2 >= rho max_{1<=j<=N/2} |R_j|^2, or 1 when
 // those bins are all zero.  Storage positions 1..N/2 hold bins 1..N/2.
+template <typename C = double2>
 __global__ __launch_bounds__(256) void k_peak(ScanArgs A, int s0, double rho)
 {
     __shared__ double shd[2 * 4];
@@ -1305,7 +1324,7 @@ __global__ __launch_bounds__(256) void k_peak(ScanArgs A, int s0, double rho)
     const SigDesc d = A.sigs[s];
     const LenPlan& lp = A.lens[d.len_id];
     const int32_t* btab = lp.spec_perm ? A.itab + lp.bin_off : nullptr;
-    const double2* R = ((A.t & 1) ? A.spec1 : A.spec0) + d.spec_off;
+    const auto R = spec_view<C>((A.t & 1) ? A.spec1 : A.spec0, d.spec_off);
     const int64_t nh = d.N / 2;
     double mn = INFINITY, mx = 0.0;
     for (int64_t p = 1 + threadIdx.x; p <= nh; p += 256) {
@@ -1381,7 +1400,7 @@ __device__ __forceinline__ int64_t geo_m(int q) { return q == 0 ? 1 : q == 1 ? 2
 // power*lambda^2 in LDS.  PRE: k_scan_prologue already ran (L and the power
 // scale are in the signal state).  SMODE: the stop mode (a compile-time copy
 // of ScanArgs::stop_mode, so the default kernel carries no other mode's work).
-template <int BPT, bool PRE, int SMODE>
+template <int BPT, bool PRE, int SMODE, typename C = double2>
 __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
 {
     constexpr int T = kScanThreads;
@@ -1414,7 +1433,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
 
     const int nh = (int)(N / 2);
     const Lam lw = make_lam(lp, A.dtab, L, A.lam ? A.lam + d.spec_off : nullptr);
-    const double2* R = ((A.t & 1) ? A.spec1 : A.spec0) + d.spec_off;
+    const auto R = spec_view<C>((A.t & 1) ? A.spec1 : A.spec0, d.spec_off);
     const double pscale = sh_d[0];
     const double delta = A.delta;
     const float d2f = (float)(delta * delta);

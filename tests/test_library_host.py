@@ -50,6 +50,7 @@ def test_options_default(lib):
     assert (o.mask_rule, o.nu, o.max_inner, o.floor_tau) == (0, 1.6, 1_000_000, 1e-9)
     assert (o.stop_mode, o.gamma, o.peak_rho) == (0, 0.0, 0.1)
     assert (o.window, o.window_points) == (None, 0)
+    assert o.precision == 0                                  # FIF_PREC_MIXED
 
 
 def _plan_status(lib, lengths, max_imfs=4, **opt):
@@ -84,6 +85,8 @@ def _plan_status(lib, lengths, max_imfs=4, **opt):
     ([4096], dict(window=[1.0, float("nan")]), -1),
     ([4096], dict(window=np.ones(65538)), -1),        # too many samples
     ([4096], dict(window=[1.0, 0.0], stop_mode=2), -1),
+    ([4096], dict(precision=2), -1),
+    ([4096], dict(precision=1, window=[1.0, 0.0]), -1),   # the FP32 lane takes no window shape
     ([], {}, -1),
 ])
 def test_plan_rejects_bad_arguments_on_host(lib, lengths, kw, status):
