@@ -255,6 +255,7 @@ fif_status set_lds_limits()
                     set((const void*)k_pass2<MODE_STEP, float, float, TL, P2, C>);
                     set((const void*)k_pass2<MODE_STEP, double, double, TL, P2, C>);
                 };
+
                 p2(std::false_type{});
                 p2(std::true_type{});
             };

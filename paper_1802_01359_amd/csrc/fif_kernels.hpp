@@ -1030,118 +1030,94 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
 
 // -------------------------------------------------- four-step pass 2 (rows)
 
-// Work tile = TR consecutive rows r' of Y.  Transforms each row over c
-// (length N1); output element N2 * c' + r'.  STEP: IMF, one run summary per
-// c' (TR consecutive samples) and the tile's min/max; FORWARD: half
-// spectrum; REMAINDER: y.
-template <int MODE, typename InT, typename OutT, int TILE = kTileCap, bool P2 = false, typename C = double2>
-__global__ __launch_bounds__(kFftThreads) void k_pass2(StepArgs A, const InT* __restrict__ x,
-                                                       OutT* __restrict__ imfs, OutT* __restrict__ rem)
+// One pass-2 work item: its signal, plan fields and rows.
+struct P2Item {
+    Work w;
+    SigDesc d;
+    const LenPlan* lp;
+    PlanRegs pr;
+    int N1, N2, TR, TC, r0, total;
+    SigState* S;
+};
+__device__ __forceinline__ P2Item p2_item(const StepArgs& A, int item)
 {
-    extern __shared__ double2 lds_raw[];
-    C* lds = reinterpret_cast<C*>(lds_raw);
-    __shared__ double shd[2 * (kFftThreads / 64)];
-    const Work w = A.work[blockIdx.x];
-    const SigDesc d = A.sigs[w.sig];
-    const LenPlan& lp = A.lens[d.len_id];
-    const PlanRegs pr = plan_regs(lp);
-    const int64_t N = d.N;
-    const int N1 = lp.N1, N2 = lp.N2, TR = lp.TR;
-    const int r0 = w.tile * TR;
-    SigState* S = A.st + w.sig;
-    const int total = TR * N1;
+    P2Item t;
+    t.w = A.work[item];
+    t.d = A.sigs[t.w.sig];
+    t.lp = A.lens + t.d.len_id;
+    t.pr = plan_regs(*t.lp);
+    t.N1 = t.lp->N1;
+    t.N2 = t.lp->N2;
+    t.TR = t.lp->TR;
+    t.TC = t.lp->TC;
+    t.r0 = t.w.tile * t.TR;
+    t.total = t.TR * t.N1;
+    t.S = A.st + t.w.sig;
+    return t;
+}
+
+// The item's TR x N1 block of the intermediate into registers.  Element
+// e = (t * TC + s) * TR + rl: consecutive lanes take consecutive rows of one
+// column, so the LDS stores of p2_stage are conflict free; the global reads
+// stay within the TR x TC run of pass-1 tile t.
+template <int TILE, typename C>
+__device__ __forceinline__ void p2_gather(const StepArgs& A, const P2Item& t, C (&yv)[TILE / kFftThreads])
+{
+    const C* Y = reinterpret_cast<const C*>(A.inter) + t.d.inter_off;
+    const FastDiv ftr = fastdiv(t.TR), ftc = fastdiv(t.TC);
+    const int64_t blk = (int64_t)t.TC * t.N2;
+#pragma unroll
+    for (int q = 0; q < TILE / kFftThreads; ++q) {
+        const int e = threadIdx.x + q * kFftThreads;
+        yv[q] = czero<C>();
+        if (e < t.total) {
+            int s, rl;
+            const int u = fdivmod(e, ftr, rl);
+            const int tt = fdivmod(u, ftc, s);
+            yv[q] = Y[(int64_t)tt * blk + (int64_t)(t.r0 + rl) * t.TC + s];
+        }
+    }
+}
+template <int TILE, typename C>
+__device__ __forceinline__ void p2_stage(const P2Item& t, const C (&yv)[TILE / kFftThreads], C* lds)
+{
+    const FastDiv ftr = fastdiv(t.TR), ftc = fastdiv(t.TC);
+#pragma unroll
+    for (int q = 0; q < TILE / kFftThreads; ++q) {
+        const int e = threadIdx.x + q * kFftThreads;
+        if (e < t.total) {
+            int s, rl;
+            const int u = fdivmod(e, ftr, rl);
+            const int tt = fdivmod(u, ftc, s);
+            lds[pass1_col(t.pr, tt, s) * t.TR + rl] = yv[q];
+        }
+    }
+}
+
+// Outer step, inactive signal: its rows of IMF t are zero.
+template <typename OutT>
+__device__ __forceinline__ void p2_zero(const StepArgs& A, const P2Item& t, OutT* __restrict__ imfs)
+{
+    OutT* row = imfs + (int64_t)A.max_imfs * t.d.off + (int64_t)A.t * t.d.N;
+    const FastDiv ftr = fastdiv(t.TR);
+    for (int f = threadIdx.x; f < t.total; f += kFftThreads) {
+        int rl;
+        const int cp = fdivmod(f, ftr, rl);
+        row[(int64_t)t.N2 * cp + t.r0 + rl] = (OutT)0;
+    }
+}
+
+// Outer step, after the row transforms: the IMF rows out of the real parts,
+// the residual (imaginary parts) counted: one run summary per column c' (TR
+// consecutive samples) and the tile's min and max; thin row tiles hand the
+// residual to k_count_resid instead.
+template <int TILE, typename OutT, typename C>
+__device__ __forceinline__ void p2_step_out(const StepArgs& A, const P2Item& t, OutT* __restrict__ imfs, C* lds,
+                                            double* shd)
+{
+    const int TR = t.TR, N1 = t.N1, N2 = t.N2, r0 = t.r0, total = t.total;
     const FastDiv ftr = fastdiv(TR);
-    if (MODE == MODE_WINDOW && !S->active) return;
-    if (MODE == MODE_STEP && w.tile == 0 && threadIdx.x == 0) S->redo = 0;   // the step is final now
-    if (MODE == MODE_STEP && !S->active) {
-        OutT* row = imfs + (int64_t)A.max_imfs * d.off + (int64_t)A.t * N;
-        for (int f = threadIdx.x; f < total; f += kFftThreads) {
-            int rl;
-            const int cp = fdivmod(f, ftr, rl);
-            row[(int64_t)N2 * cp + r0 + rl] = (OutT)0;
-        }
-        return;
-    }
-    if (MODE == MODE_REMAINDER && S->status != 0) {
-        for (int f = threadIdx.x; f < total; f += kFftThreads) {
-            int rl;
-            const int cp = fdivmod(f, ftr, rl);
-            const int64_t n = (int64_t)N2 * cp + r0 + rl;
-            rem[d.off + n] = (OutT)x[d.off + n];
-        }
-        return;
-    }
-    const C* Y = reinterpret_cast<const C*>(A.inter) + d.inter_off;
-    {
-        // e = (t * TC + s) * TR + rl: consecutive lanes take consecutive
-        // rows of one column, so the LDS stores below are conflict free;
-        // the global reads stay within the TR x TC run of pass-1 tile t
-        const int TC = lp.TC;
-        const FastDiv ftc = fastdiv(TC);
-        const int64_t blk = (int64_t)TC * N2;
-        constexpr int GQ = TILE / kFftThreads;
-        C yv[GQ];
-#pragma unroll
-        for (int q = 0; q < GQ; ++q) {
-            const int e = threadIdx.x + q * kFftThreads;
-            yv[q] = czero<C>();
-            if (e < total) {
-                int s, rl;
-                const int u = fdivmod(e, ftr, rl);
-                const int t = fdivmod(u, ftc, s);
-                yv[q] = Y[(int64_t)t * blk + (int64_t)(r0 + rl) * TC + s];
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < GQ; ++q) {
-            const int e = threadIdx.x + q * kFftThreads;
-            if (e < total) {
-                int s, rl;
-                const int u = fdivmod(e, ftr, rl);
-                const int t = fdivmod(u, ftc, s);
-                lds[pass1_col(pr, t, s) * TR + rl] = yv[q];
-            }
-        }
-    }
-    __syncthreads();
-    if (fwd_mode(MODE))
-        lds_fft<false, TILE, P2>(lds, lp.f2, TR, A.ctab);
-    else
-        lds_fft<true, TILE, P2>(lds, lp.f2, TR, A.ctab);
-    if (MODE == MODE_WINDOW) {
-        double* lt = A.lam + d.spec_off;
-        const double inv = 1.0 / A.wsum[w.sig];
-        const int64_t nh = N / 2;
-        for (int f = threadIdx.x; f < total; f += kFftThreads) {
-            int rl;
-            const int cp = fdivmod(f, ftr, rl);
-            const int64_t n = (int64_t)N2 * cp + r0 + rl;
-            if (n <= nh) lt[n] = window_lambda(n, lds[f].x, inv);
-        }
-        return;
-    }
-    if (MODE == MODE_FORWARD) {
-        C* out = reinterpret_cast<C*>(A.spec0) + d.spec_off;
-        const int64_t nh = N / 2;
-        for (int f = threadIdx.x; f < total; f += kFftThreads) {
-            int rl;
-            const int cp = fdivmod(f, ftr, rl);
-            const int64_t n = (int64_t)N2 * cp + r0 + rl;
-            if (n <= nh) out[spec_pos(lp, n)] = lds[f];
-        }
-        return;
-    }
-    if (MODE == MODE_REMAINDER) {
-        for (int f = threadIdx.x; f < total; f += kFftThreads) {
-            int rl;
-            const int cp = fdivmod(f, ftr, rl);
-            rem[d.off + (int64_t)N2 * cp + r0 + rl] = (OutT)lds[f].y;
-        }
-        return;
-    }
-    OutT* row = imfs + (int64_t)A.max_imfs * d.off + (int64_t)A.t * N;
-    // IMF row out of the real parts; the imaginary parts (the residual) are
-    // kept in registers
+    OutT* row = imfs + (int64_t)A.max_imfs * t.d.off + (int64_t)A.t * t.d.N;
     constexpr int EQ = TILE / kFftThreads;
     double yv[EQ];
 #pragma unroll
@@ -1156,9 +1132,8 @@ __global__ __launch_bounds__(kFftThreads) void k_pass2(StepArgs A, const InT* __
             yv[q] = v.y;
         }
     }
-    if (d.resid_off >= 0) {
-        // thin row tiles: hand the residual to k_count_resid
-        double* y = A.resid + d.resid_off;
+    if (t.d.resid_off >= 0) {
+        double* y = A.resid + t.d.resid_off;
 #pragma unroll
         for (int q = 0; q < EQ; ++q) {
             const int f = threadIdx.x + q * kFftThreads;
@@ -1194,13 +1169,90 @@ __global__ __launch_bounds__(kFftThreads) void k_pass2(StepArgs A, const InT* __
             mn = fmin(mn, y);
             mx = fmax(mx, y);
         }
-        A.parts[d.part_off + cp * runs_per_row + w.tile] = r;
+        A.parts[t.d.part_off + cp * runs_per_row + t.w.tile] = r;
     }
     block_minmax<kFftThreads>(mn, mx, shd);
     if (threadIdx.x == 0) {
-        atomicMin(&S->kmin, dkey(mn));
-        atomicMax(&S->kmax, dkey(mx));
+        atomicMin(&t.S->kmin, dkey(mn));
+        atomicMax(&t.S->kmax, dkey(mx));
     }
+}
+
+// Work tile = TR consecutive rows r' of Y.  Transforms each row over c
+// (length N1); output element N2 * c' + r'.  STEP: IMF, one run summary per
+// c' (TR consecutive samples) and the tile's min/max; FORWARD: half
+// spectrum; REMAINDER: y.
+template <int MODE, typename InT, typename OutT, int TILE = kTileCap, bool P2 = false, typename C = double2>
+__global__ __launch_bounds__(kFftThreads) void k_pass2(StepArgs A, const InT* __restrict__ x,
+                                                       OutT* __restrict__ imfs, OutT* __restrict__ rem)
+{
+    extern __shared__ double2 lds_raw[];
+    C* lds = reinterpret_cast<C*>(lds_raw);
+    __shared__ double shd[2 * (kFftThreads / 64)];
+    const P2Item t = p2_item(A, blockIdx.x);
+    const SigDesc& d = t.d;
+    const LenPlan& lp = *t.lp;
+    const int64_t N = d.N;
+    const int N2 = t.N2, r0 = t.r0, total = t.total;
+    SigState* S = t.S;
+    const FastDiv ftr = fastdiv(t.TR);
+    if (MODE == MODE_WINDOW && !S->active) return;
+    if (MODE == MODE_STEP && t.w.tile == 0 && threadIdx.x == 0) S->redo = 0;   // the step is final now
+    if (MODE == MODE_STEP && !S->active) {
+        p2_zero(A, t, imfs);
+        return;
+    }
+    if (MODE == MODE_REMAINDER && S->status != 0) {
+        for (int f = threadIdx.x; f < total; f += kFftThreads) {
+            int rl;
+            const int cp = fdivmod(f, ftr, rl);
+            const int64_t n = (int64_t)N2 * cp + r0 + rl;
+            rem[d.off + n] = (OutT)x[d.off + n];
+        }
+        return;
+    }
+    {
+        C yv[TILE / kFftThreads];
+        p2_gather<TILE>(A, t, yv);
+        p2_stage<TILE>(t, yv, lds);
+    }
+    __syncthreads();
+    if (fwd_mode(MODE))
+        lds_fft<false, TILE, P2>(lds, lp.f2, t.TR, A.ctab);
+    else
+        lds_fft<true, TILE, P2>(lds, lp.f2, t.TR, A.ctab);
+    if (MODE == MODE_WINDOW) {
+        double* lt = A.lam + d.spec_off;
+        const double inv = 1.0 / A.wsum[t.w.sig];
+        const int64_t nh = N / 2;
+        for (int f = threadIdx.x; f < total; f += kFftThreads) {
+            int rl;
+            const int cp = fdivmod(f, ftr, rl);
+            const int64_t n = (int64_t)N2 * cp + r0 + rl;
+            if (n <= nh) lt[n] = window_lambda(n, lds[f].x, inv);
+        }
+        return;
+    }
+    if (MODE == MODE_FORWARD) {
+        C* out = reinterpret_cast<C*>(A.spec0) + d.spec_off;
+        const int64_t nh = N / 2;
+        for (int f = threadIdx.x; f < total; f += kFftThreads) {
+            int rl;
+            const int cp = fdivmod(f, ftr, rl);
+            const int64_t n = (int64_t)N2 * cp + r0 + rl;
+            if (n <= nh) out[spec_pos(lp, n)] = lds[f];
+        }
+        return;
+    }
+    if (MODE == MODE_REMAINDER) {
+        for (int f = threadIdx.x; f < total; f += kFftThreads) {
+            int rl;
+            const int cp = fdivmod(f, ftr, rl);
+            rem[d.off + (int64_t)N2 * cp + r0 + rl] = (OutT)lds[f].y;
+        }
+        return;
+    }
+    p2_step_out<TILE>(A, t, imfs, lds, shd);
 }
 
 // ------------------------------------------------------------------- scan --
