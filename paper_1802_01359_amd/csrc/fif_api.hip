@@ -114,7 +114,9 @@ struct fif_plan {
     struct Group {
         int32_t s0 = 0, s1 = 0;
         Range single, p1, p2, ssmall, sbig, btile, count;
-        bool big_defer = false;     // a signal of the multi-workgroup search may defer its FP64 check
+        // signals of the multi-workgroup search that defer their FP64 check
+        // (at most kBigDeferTiles tiles): some of them, all of them
+        bool big_defer_any = false, big_defer_all = true;
     };
     std::vector<Group> groups;      // groups[0] is the whole batch when only one
     Group all;
@@ -686,8 +688,11 @@ fif_status create_plan(fif_plan** out, const int64_t* lengths, int32_t B, int32_
             g.count = sub(p->w_count, s0, s1);
             g.ssmall = subi(p->scan_small, s0, s1);
             g.sbig = subi(p->scan_big, s0, s1);
-            for (int32_t i = 0; i < g.sbig.count; ++i)
-                g.big_defer = g.big_defer || p->sigs[p->scan_big[g.sbig.begin + i]].n_btiles <= kBigDeferTiles;
+            for (int32_t i = 0; i < g.sbig.count; ++i) {
+                const bool dfr = p->sigs[p->scan_big[g.sbig.begin + i]].n_btiles <= kBigDeferTiles;
+                g.big_defer_any = g.big_defer_any || dfr;
+                g.big_defer_all = g.big_defer_all && dfr;
+            }
             return g;
         };
         p->all = make_group(0, B);
@@ -1143,10 +1148,19 @@ void launch_scan(const fif_plan* p, Bound& b, int t, void* ws, hipStream_t s, co
     if (nb) {
         Timed tm(p, "scan_big", s);
         S.list = p->d_scan_big + g.sbig.begin;
-        k_bscan_round<kScanThreads, true, C><<<nt, kScanThreads, 0, s>>>(S, btile);
+        // stop mode 0 hands the FP32 estimates to pass 1's check: when every
+        // signal of the group defers, the rounds are FP32 rounds only
+        const bool fp32_only = p->opt.stop_mode == 0 && S.defer && g.big_defer_all;
+        if (fp32_only)
+            k_bscan_round<kScanThreads, true, C, 1><<<nt, kScanThreads, 0, s>>>(S, btile);
+        else
+            k_bscan_round<kScanThreads, true, C, 0><<<nt, kScanThreads, 0, s>>>(S, btile);
         k_bscan_decide<C><<<nb, 64 * kDecideGroups, 0, s>>>(S);
         for (int r = 0; r < kBigRounds; ++r) {
-            k_bscan_round<kScanThreads, false, C><<<nt, kScanThreads, 0, s>>>(S, btile);
+            if (fp32_only)
+                k_bscan_round<kScanThreads, false, C, 1><<<nt, kScanThreads, 0, s>>>(S, btile);
+            else
+                k_bscan_round<kScanThreads, false, C, 0><<<nt, kScanThreads, 0, s>>>(S, btile);
             k_bscan_decide<C><<<nb, 64 * kDecideGroups, 0, s>>>(S);
         }
         k_bscan_final<kScanThreads><<<nb, 64, 0, s>>>(S);
@@ -1171,7 +1185,7 @@ void launch_step_c(const fif_plan* p, Bound& b, int t, const T* x, T* imfs, void
             Timed tm(p, "pass1_step", s);
             run_pass1<MODE_STEP, T, false, C>(p, (unsigned)g.p1.count, s, A, x);
         }
-        const unsigned nb = g.big_defer ? (unsigned)g.sbig.count : 0u, nt = (unsigned)g.btile.count;
+        const unsigned nb = g.big_defer_any ? (unsigned)g.sbig.count : 0u, nt = (unsigned)g.btile.count;
         if (b.sc.defer && (g.ssmall.count || nb)) {
             // deferred FP64 check of m, then the rare redo: exact search and
             // pass 1 again for the signals whose check failed
@@ -1200,7 +1214,7 @@ void launch_step_c(const fif_plan* p, Bound& b, int t, const T* x, T* imfs, void
                 const Work* btile = p->d_btile + g.btile.begin;
                 k_bscan_redo_prep<<<nb, 64, 0, s>>>(V);
                 for (int r = 0; r < kBigRedoRounds; ++r) {
-                    k_bscan_round<kScanThreads, false, C><<<nt, kScanThreads, 0, s>>>(V, btile);
+                    k_bscan_round<kScanThreads, false, C, 2><<<nt, kScanThreads, 0, s>>>(V, btile);
                     k_bscan_decide<C><<<nb, 64 * kDecideGroups, 0, s>>>(V);
                 }
                 k_bscan_final<kScanThreads><<<nb, 64, 0, s>>>(V);

@@ -150,7 +150,9 @@ __device__ __forceinline__ void wave_reduce_scatter(float* v, int lane)
     }
 }
 
-template <int T, int BPT, typename C>
+// PHS: 0 both kinds of round, 1 FP32 rounds only, 2 FP64 rounds only (a
+// kernel without the other kind's code needs fewer registers).
+template <int T, int BPT, typename C, int PHS>
 __device__ __forceinline__ void bscan_tile_sums(const ScanArgs& A, const SigDesc& d, const LenPlan& lp,
                                                 const BigScan* G, int tile, double* out, float* shf,
                                                 double* shd)
@@ -161,7 +163,7 @@ __device__ __forceinline__ void bscan_tile_sums(const ScanArgs& A, const SigDesc
     const int ph = G->phase;
     const int nc = G->ncand;
     const auto R = spec_view<C>((A.t & 1) ? A.spec1 : A.spec0, d.spec_off);
-    if (ph < 2) {
+    if (PHS == 1 || (PHS == 0 && ph < 2)) {
         const float* tau = A.gscr + d.gs_off;
         const float* av = tau + nh;
         const float* bv = av + nh;
@@ -556,7 +558,7 @@ __device__ __forceinline__ void bscan_decide(const ScanArgs& A, int s, const Sig
 }
 
 // One candidate round over one tile (first round: also fill the scratch).
-template <int T, bool SWEEP, typename C = double2>
+template <int T, bool SWEEP, typename C = double2, int PHS = 0>
 __global__ __launch_bounds__(T) void k_bscan_round(ScanArgs A, const Work* __restrict__ work)
 {
     constexpr int BPT = kBigTile / T;
@@ -568,7 +570,7 @@ __global__ __launch_bounds__(T) void k_bscan_round(ScanArgs A, const Work* __res
     const LenPlan& lp = A.lens[d.len_id];
     BigScan* G = A.bigs + d.bs;
     const int ph = G->phase;
-    if (ph >= 3) return;
+    if (ph >= 3 || (PHS == 1 && ph == 2) || (PHS == 2 && ph < 2)) return;
     if (SWEEP) {
         const int nh = (int)(d.N / 2);
         float* tau = A.gscr + d.gs_off;
@@ -618,7 +620,7 @@ __global__ __launch_bounds__(T) void k_bscan_round(ScanArgs A, const Work* __res
         if (threadIdx.x == 0) A.bqmax[d.bt_off + w.tile] = qmx;
         // each thread reads back only its own bins below
     }
-    bscan_tile_sums<T, BPT, C>(A, d, lp, G, w.tile, shv, shf, shd);
+    bscan_tile_sums<T, BPT, C, PHS>(A, d, lp, G, w.tile, shv, shf, shd);
     double* P = A.bpart + ((int64_t)d.bt_off + w.tile) * 2 * kBigCand;
     const int nc = G->ncand;
     if (threadIdx.x < 2 * nc) P[threadIdx.x] = shv[threadIdx.x];
