@@ -738,13 +738,18 @@ __global__ __launch_bounds__(T) void k_bscan_final(ScanArgs A)
 }
 
 // Run summaries, min and max of the FP64 residual written by k_pass2 for
-// signals whose row tiles are too thin for per-tile summaries.
+// signals whose row tiles are too thin for per-tile summaries.  A workgroup
+// takes kFftCap samples in halves staged through LDS (coalesced loads; each
+// thread then walks a run of consecutive samples); the halves' summaries
+// are combined in sample order.
 __global__ __launch_bounds__(kFftThreads) void k_count_resid(const SigDesc* __restrict__ sigs,
                                                               const Work* __restrict__ work,
                                                               const double* __restrict__ resid,
                                                               RunState* __restrict__ parts,
                                                               SigState* __restrict__ st)
 {
+    constexpr int H = kFftCap / 2;
+    __shared__ double stg[H];
     __shared__ RunState sh[kFftThreads / 64];
     __shared__ double shd[2 * (kFftThreads / 64)];
     const Work w = work[blockIdx.x];
@@ -752,20 +757,29 @@ __global__ __launch_bounds__(kFftThreads) void k_count_resid(const SigDesc* __re
     if (!st[w.sig].active) return;
     const int64_t t0 = (int64_t)w.tile * kFftCap;
     const int64_t len = min((int64_t)kFftCap, d.N - t0);
-    const int chunk = (int)((len + kFftThreads - 1) / kFftThreads);
-    const int64_t a = (int64_t)threadIdx.x * chunk, b = min(len, a + chunk);
-    RunState r = run_empty();
+    const double* src = resid + d.resid_off + t0;
+    RunState tot = run_empty();
     double mn = INFINITY, mx = -INFINITY;
-    for (int64_t i = a; i < b; ++i) {
-        const double v = resid[d.resid_off + t0 + i];
-        run_push(r, v);
-        mn = fmin(mn, v);
-        mx = fmax(mx, v);
+    for (int h = 0; h < 2; ++h) {
+        const int cnt = (int)max((int64_t)0, min((int64_t)H, len - (int64_t)h * H));
+        for (int i = threadIdx.x; i < cnt; i += kFftThreads) stg[i] = src[(int64_t)h * H + i];
+        __syncthreads();
+        const int chunk = (cnt + kFftThreads - 1) / kFftThreads;
+        const int a = threadIdx.x * chunk, b = min(cnt, a + chunk);
+        RunState r = run_empty();
+        for (int i = a; i < b; ++i) {
+            const double v = stg[i];
+            run_push(r, v);
+            mn = fmin(mn, v);
+            mx = fmax(mx, v);
+        }
+        r = block_run_reduce<kFftThreads>(r, sh);
+        if (threadIdx.x == 0) tot = run_combine(tot, r);
+        __syncthreads();
     }
     block_minmax<kFftThreads>(mn, mx, shd);
-    r = block_run_reduce<kFftThreads>(r, sh);
     if (threadIdx.x == 0) {
-        parts[d.part_off + w.tile] = r;
+        parts[d.part_off + w.tile] = tot;
         atomicMin(&st[w.sig].kmin, dkey(mn));
         atomicMax(&st[w.sig].kmax, dkey(mx));
     }
