@@ -1149,18 +1149,15 @@ void launch_scan(const fif_plan* p, Bound& b, int t, void* ws, hipStream_t s, co
         Timed tm(p, "scan_big", s);
         S.list = p->d_scan_big + g.sbig.begin;
         // stop mode 0 hands the FP32 estimates to pass 1's check: when every
-        // signal of the group defers, the rounds are FP32 rounds only
+        // signal of the group defers, the rounds are FP32 rounds only; else
+        // each round is an FP32 and an FP64 kernel, each working on the
+        // signals in its own phase (one decide after both)
         const bool fp32_only = p->opt.stop_mode == 0 && S.defer && g.big_defer_all;
-        if (fp32_only)
-            k_bscan_round<kScanThreads, true, C, 1><<<nt, kScanThreads, 0, s>>>(S, btile);
-        else
-            k_bscan_round<kScanThreads, true, C, 0><<<nt, kScanThreads, 0, s>>>(S, btile);
+        k_bscan_round<kScanThreads, true, C, 1><<<nt, kScanThreads, 0, s>>>(S, btile);
         k_bscan_decide<C><<<nb, 64 * kDecideGroups, 0, s>>>(S);
         for (int r = 0; r < kBigRounds; ++r) {
-            if (fp32_only)
-                k_bscan_round<kScanThreads, false, C, 1><<<nt, kScanThreads, 0, s>>>(S, btile);
-            else
-                k_bscan_round<kScanThreads, false, C, 0><<<nt, kScanThreads, 0, s>>>(S, btile);
+            k_bscan_round<kScanThreads, false, C, 1><<<nt, kScanThreads, 0, s>>>(S, btile);
+            if (!fp32_only) k_bscan_round<kScanThreads, false, C, 2><<<nt, kScanThreads, 0, s>>>(S, btile);
             k_bscan_decide<C><<<nb, 64 * kDecideGroups, 0, s>>>(S);
         }
         k_bscan_final<kScanThreads><<<nb, 64, 0, s>>>(S);

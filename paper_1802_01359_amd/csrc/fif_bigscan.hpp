@@ -150,8 +150,9 @@ __device__ __forceinline__ void wave_reduce_scatter(float* v, int lane)
     }
 }
 
-// PHS: 0 both kinds of round, 1 FP32 rounds only, 2 FP64 rounds only (a
-// kernel without the other kind's code needs fewer registers).
+// PHS: 1 the FP32 rounds (phases 0 and 1), 2 the FP64 rounds (phase 2).  A
+// kernel holds one kind's code only: the FP32 kind then fits in 128 VGPRs,
+// two workgroups per CU.
 template <int T, int BPT, typename C, int PHS>
 __device__ __forceinline__ void bscan_tile_sums(const ScanArgs& A, const SigDesc& d, const LenPlan& lp,
                                                 const BigScan* G, int tile, double* out, float* shf,
@@ -163,7 +164,7 @@ __device__ __forceinline__ void bscan_tile_sums(const ScanArgs& A, const SigDesc
     const int ph = G->phase;
     const int nc = G->ncand;
     const auto R = spec_view<C>((A.t & 1) ? A.spec1 : A.spec0, d.spec_off);
-    if (PHS == 1 || (PHS == 0 && ph < 2)) {
+    if (PHS == 1) {
         const float* tau = A.gscr + d.gs_off;
         const float* av = tau + nh;
         const float* bv = av + nh;
@@ -202,52 +203,72 @@ __device__ __forceinline__ void bscan_tile_sums(const ScanArgs& A, const SigDesc
         float acc[2 * kBigCand];
 #pragma unroll
         for (int i = 0; i < 2 * kBigCand; ++i) acc[i] = 0.f;
-        // all of the thread's bins are loaded first (one memory round trip);
-        // bins past the end of the signal carry a = b = 0
-        float tq[BPT], aq[BPT], bq[BPT];
+        // the thread's bins in chunks of CH, each chunk's loads issued
+        // together (one memory round trip per chunk; the chunk loop is kept
+        // rolled so that only one chunk's values occupy registers); bins past
+        // the end of the signal carry a = b = 0
+        constexpr int CH = BPT < 8 ? BPT : 8;
+        auto load_chunk = [&](int q0, float* tq, float* aq, float* bq) {
 #pragma unroll
-        for (int q = 0; q < BPT; ++q) {
-            const int j = j0 + tid + q * T;
-            tq[q] = 0.f;
-            aq[q] = 0.f;
-            bq[q] = 0.f;
-            if (j <= nh) {
-                tq[q] = tau[j - 1];
-                aq[q] = av[j - 1];
-                bq[q] = bv[j - 1];
+            for (int q = 0; q < CH; ++q) {
+                const int j = j0 + tid + (q0 + q) * T;
+                tq[q] = 0.f;
+                aq[q] = 0.f;
+                bq[q] = 0.f;
+                if (j <= nh) {
+                    tq[q] = tau[j - 1];
+                    aq[q] = av[j - 1];
+                    bq[q] = bv[j - 1];
+                }
             }
-        }
+        };
         if (pat == 0) {
-#pragma unroll
-            for (int q = 0; q < BPT; ++q) {
-                const float tj = tq[q], aj = aq[q], bj = bq[q];
+            // one exp2 per candidate and bin; the exponents come from LDS,
+            // read anew in every chunk (the compiler barrier keeps the 32
+            // values from being held in registers across the chunks)
+            __shared__ float she[kBigCand];
+            if (tid < kBigCand) she[tid] = tid < nc ? (float)(G->cand[tid] - 1) : 0.f;
+            __syncthreads();
+#pragma unroll 1
+            for (int q0 = 0; q0 < BPT; q0 += CH) {
+                asm volatile("" ::: "memory");
+                float tq[CH], aq[CH], bq[CH];
+                load_chunk(q0, tq, aq, bq);
 #pragma unroll
                 for (int i = 0; i < kBigCand; ++i) {
                     if (i < nc) {
-                        const float ei = (float)(G->cand[i] - 1);
-                        const float x = (ei == 0.f) ? 1.f : __builtin_amdgcn_exp2f(ei * tj);
-                        acc[2 * i] += aj * x;
-                        acc[2 * i + 1] += bj * x;
+                        const float ei = she[i];
+#pragma unroll
+                        for (int q = 0; q < CH; ++q) {
+                            const float x = (ei == 0.f) ? 1.f : __builtin_amdgcn_exp2f(ei * tq[q]);
+                            acc[2 * i] += aq[q] * x;
+                            acc[2 * i + 1] += bq[q] * x;
+                        }
                     }
                 }
             }
         } else {
+#pragma unroll 1
+            for (int q0 = 0; q0 < BPT; q0 += CH) {
+                float tq[CH], aq[CH], bq[CH];
+                load_chunk(q0, tq, aq, bq);
 #pragma unroll
-            for (int q = 0; q < BPT; ++q) {
-                const float tj = tq[q], aj = aq[q], bj = bq[q];
-                float x = (e0 == 0.f) ? 1.f : __builtin_amdgcn_exp2f(e0 * tj);
-                float r = __builtin_amdgcn_exp2f(d1f * tj);
-                const float xl = __builtin_amdgcn_exp2f(elast * tj);
+                for (int q = 0; q < CH; ++q) {
+                    const float tj = tq[q], aj = aq[q], bj = bq[q];
+                    float x = (e0 == 0.f) ? 1.f : __builtin_amdgcn_exp2f(e0 * tj);
+                    float r = __builtin_amdgcn_exp2f(d1f * tj);
+                    const float xl = __builtin_amdgcn_exp2f(elast * tj);
 #pragma unroll
-                for (int i = 0; i < kBigCand; ++i) {
-                    if (i < nc) {
-                        if (i > 0) {
-                            x *= r;
-                            r = dbl ? r * r : r;
+                    for (int i = 0; i < kBigCand; ++i) {
+                        if (i < nc) {
+                            if (i > 0) {
+                                x *= r;
+                                r = dbl ? r * r : r;
+                            }
+                            const float xi = (fresh_last && i == nc - 1) ? xl : x;
+                            acc[2 * i] += aj * xi;
+                            acc[2 * i + 1] += bj * xi;
                         }
-                        const float xi = (fresh_last && i == nc - 1) ? xl : x;
-                        acc[2 * i] += aj * xi;
-                        acc[2 * i + 1] += bj * xi;
                     }
                 }
             }
@@ -558,9 +579,15 @@ __device__ __forceinline__ void bscan_decide(const ScanArgs& A, int s, const Sig
 }
 
 // One candidate round over one tile (first round: also fill the scratch).
-template <int T, bool SWEEP, typename C = double2, int PHS = 0>
+// PHS as for bscan_tile_sums: a round launches the FP32 kind and, unless every
+// signal of the group leaves its FP64 check to pass 1, the FP64 kind after it;
+// each skips the signals in the other kind's phase.  Every active signal
+// enters the sweep in phase 0.
+template <int T, bool SWEEP, typename C, int PHS>
 __global__ __launch_bounds__(T) void k_bscan_round(ScanArgs A, const Work* __restrict__ work)
 {
+    static_assert(PHS == 1 || PHS == 2, "one kind of round per kernel");
+    static_assert(!SWEEP || PHS == 1, "the sweep opens the FP32 phase");
     constexpr int BPT = kBigTile / T;
     __shared__ double shd[4 * (T / 64)];
     __shared__ float shf[64 * (T / 64)];
@@ -570,7 +597,7 @@ __global__ __launch_bounds__(T) void k_bscan_round(ScanArgs A, const Work* __res
     const LenPlan& lp = A.lens[d.len_id];
     BigScan* G = A.bigs + d.bs;
     const int ph = G->phase;
-    if (ph >= 3 || (PHS == 1 && ph == 2) || (PHS == 2 && ph < 2)) return;
+    if (ph >= 3 || (PHS == 1) != (ph < 2)) return;
     if (SWEEP) {
         const int nh = (int)(d.N / 2);
         float* tau = A.gscr + d.gs_off;
