@@ -117,6 +117,8 @@ struct fif_plan {
         // signals of the multi-workgroup search that defer their FP64 check
         // (at most kBigDeferTiles tiles): some of them, all of them
         bool big_defer_any = false, big_defer_all = true;
+        // kinds among the one-workgroup scan's signals: four-step, one pass
+        bool small_two_pass = false, small_one_pass = false;
     };
     std::vector<Group> groups;      // groups[0] is the whole batch when only one
     Group all;
@@ -265,6 +267,8 @@ fif_status set_lds_limits()
             tiles(std::integral_constant<int, kTileCapBig>{});
             set((const void*)k_scan<kScanBinsPerThread, false, 0, C>);
             set((const void*)k_scan<kScanBinsPerThread, true, 0, C>);
+            set((const void*)k_scan<kScanBinsDeferred, false, 0, C, true>);
+            set((const void*)k_scan<kScanBinsDeferred, true, 0, C, true>);
             set((const void*)k_scan<kScanBinsPerThread, false, 1, C>);
             set((const void*)k_scan<kScanBinsPerThread, true, 1, C>);
             set((const void*)k_scan<kScanBinsPerThread, false, 2, C>);
@@ -608,7 +612,7 @@ fif_status create_plan(fif_plan** out, const int64_t* lengths, int32_t B, int32_
         d.n_btiles = 0;
         d.gs_off = 0;
         d.p1_off = (int32_t)p->w_p1.size();
-        if (N / 2 > (int64_t)kScanBinsPerThread * kScanThreads) {
+        if (N / 2 > (int64_t)kScanBins) {
             d.bs = nbig++;
             d.bt_off = btiles;
             d.n_btiles = (int32_t)((N / 2 + kBigTile - 1) / kBigTile);
@@ -688,6 +692,11 @@ fif_status create_plan(fif_plan** out, const int64_t* lengths, int32_t B, int32_
             g.count = sub(p->w_count, s0, s1);
             g.ssmall = subi(p->scan_small, s0, s1);
             g.sbig = subi(p->scan_big, s0, s1);
+            for (int32_t i = 0; i < g.ssmall.count; ++i) {
+                const bool tp = p->lens[p->sigs[p->scan_small[g.ssmall.begin + i]].len_id].two_pass != 0;
+                g.small_two_pass = g.small_two_pass || tp;
+                g.small_one_pass = g.small_one_pass || !tp;
+            }
             for (int32_t i = 0; i < g.sbig.count; ++i) {
                 const bool dfr = p->sigs[p->scan_big[g.sbig.begin + i]].n_btiles <= kBigDeferTiles;
                 g.big_defer_any = g.big_defer_any || dfr;
@@ -1032,14 +1041,20 @@ void launch_init(const fif_plan* p, Bound& b, const T* x, hipStream_t s)
 }
 
 template <bool PRE, typename C = double2>
-void launch_k_scan(int mode, int n, size_t lds, hipStream_t s, const ScanArgs& S)
+void launch_k_scan(int mode, int n, size_t lds, hipStream_t s, const ScanArgs& S, const fif_plan::Group& g)
 {
-    if (mode == 1)
-        k_scan<kScanBinsPerThread, PRE, 1, C><<<(unsigned)n, kScanThreads, lds, s>>>(S);
-    else if (mode == 2)
-        k_scan<kScanBinsPerThread, PRE, 2, C><<<(unsigned)n, kScanThreads, lds, s>>>(S);
-    else
-        k_scan<kScanBinsPerThread, PRE, 0, C><<<(unsigned)n, kScanThreads, lds, s>>>(S);
+    constexpr unsigned TG = kScanBins / kScanBinsPerThread, TD = kScanBins / kScanBinsDeferred;
+    if (mode == 1) {
+        k_scan<kScanBinsPerThread, PRE, 1, C><<<(unsigned)n, TG, lds, s>>>(S);
+    } else if (mode == 2) {
+        k_scan<kScanBinsPerThread, PRE, 2, C><<<(unsigned)n, TG, lds, s>>>(S);
+    } else if (S.defer && !S.redo_only && !g.small_one_pass) {
+        // four-step signals only: the FP32 search (their FP64 check is in
+        // pass 1), in the kernel without the FP64 search
+        k_scan<kScanBinsDeferred, PRE, 0, C, true><<<(unsigned)n, TD, lds, s>>>(S);
+    } else {
+        k_scan<kScanBinsPerThread, PRE, 0, C><<<(unsigned)n, TG, lds, s>>>(S);
+    }
 }
 
 // Eigenvalue tables of a sampled window shape for the active signals of one
@@ -1077,7 +1092,7 @@ void launch_scan(const fif_plan* p, Bound& b, int t, void* ws, hipStream_t s, co
     const bool split = p->model || p->rec || !p->wshape.empty();
     const unsigned nb = (unsigned)g.sbig.count, nt = (unsigned)g.btile.count;
     const Work* btile = p->d_btile + g.btile.begin;
-    const size_t scan_lds = sizeof(float) * kScanBinsPerThread * kScanThreads;
+    const size_t scan_lds = sizeof(float) * kScanBins;
     if (p->opt.mask_rule == 2) {
         Timed tm(p, "peak", s);
         k_peak<C><<<(unsigned)(g.s1 - g.s0), 256, 0, s>>>(S, g.s0, p->opt.peak_rho);
@@ -1086,7 +1101,7 @@ void launch_scan(const fif_plan* p, Bound& b, int t, void* ws, hipStream_t s, co
         if (g.ssmall.count) {
             S.list = p->d_scan_small + g.ssmall.begin;
             Timed tm(p, "scan", s);
-            launch_k_scan<false, C>(p->opt.stop_mode, g.ssmall.count, scan_lds, s, S);
+            launch_k_scan<false, C>(p->opt.stop_mode, g.ssmall.count, scan_lds, s, S, g);
         }
         if (nb) {
             Timed tm(p, "scan_big", s);
@@ -1138,7 +1153,7 @@ void launch_scan(const fif_plan* p, Bound& b, int t, void* ws, hipStream_t s, co
         if (g.ssmall.count) {
             S.list = p->d_scan_small + g.ssmall.begin;
             Timed tm(p, "scan", s);
-            launch_k_scan<true, C>(p->opt.stop_mode, g.ssmall.count, scan_lds, s, S);
+            launch_k_scan<true, C>(p->opt.stop_mode, g.ssmall.count, scan_lds, s, S, g);
         }
         if (nb && p->model) {
             S.list = p->d_scan_big + g.sbig.begin;
@@ -1202,7 +1217,7 @@ void launch_step_c(const fif_plan* p, Bound& b, int t, const T* x, T* imfs, void
             V.redo_only = 1;
             if (g.ssmall.count) {
                 V.list = small;
-                launch_k_scan<true, C>(0, g.ssmall.count, sizeof(float) * kScanBinsPerThread * kScanThreads, s, V);
+                launch_k_scan<true, C>(0, g.ssmall.count, sizeof(float) * kScanBins, s, V, g);
             }
             if (nb) {
                 // FP64 rounds of the multi-workgroup search for the signals

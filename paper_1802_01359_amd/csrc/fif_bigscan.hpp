@@ -1,5 +1,5 @@
 // Search for m when a signal has more spectrum bins than one workgroup holds
-// (N/2 > kScanBinsPerThread * kScanThreads).  Same mathematics as k_scan
+// (N/2 > kScanBins).  Same mathematics as k_scan
 // (smallest m with SD_m <= delta, SD by Parseval, FP32 bracketing then FP64
 // confirmation), spread over tiles of kBigTile bins:
 //

@@ -1447,15 +1447,18 @@ __device__ __forceinline__ int64_t apriori_n0(double mzb, int64_t L, int64_t N, 
 constexpr int kGeo = 12;
 __device__ __forceinline__ int64_t geo_m(int q) { return q == 0 ? 1 : q == 1 ? 2 : ((int64_t)1 << (2 * (q - 1))); }
 
-// One workgroup per signal with at most BPT * kScanThreads bins: thread-owned
-// bins j = 1 + tid + i*T (i < BPT) keep log2(mu) and the power in registers,
-// power*lambda^2 in LDS.  PRE: k_scan_prologue already ran (L and the power
-// scale are in the signal state).  SMODE: the stop mode (a compile-time copy
-// of ScanArgs::stop_mode, so the default kernel carries no other mode's work).
-template <int BPT, bool PRE, int SMODE, typename C = double2>
-__global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
+// One workgroup per signal with at most kScanBins bins, T = kScanBins / BPT
+// threads: thread-owned bins j = 1 + tid + i*T (i < BPT) keep log2(mu) and the
+// power in registers, power*lambda^2 in LDS.  PRE: k_scan_prologue already ran
+// (L and the power scale are in the signal state).  SMODE: the stop mode (a
+// compile-time copy of ScanArgs::stop_mode, so the default kernel carries no
+// other mode's work).  DEF: the kernel for lists of four-step signals whose
+// FP64 check (stop mode 0) is deferred to pass 1 -- the FP32 search only.
+template <int BPT, bool PRE, int SMODE, typename C = double2, bool DEF = false>
+__global__ __launch_bounds__(kScanBins / BPT) void k_scan(ScanArgs A)
 {
-    constexpr int T = kScanThreads;
+    static_assert(!DEF || SMODE == 0, "only stop mode 0 defers its check");
+    constexpr int T = kScanBins / BPT;
     constexpr int NR = BPT;
     __shared__ RunState shr[T / 64];
     __shared__ double shd[4 * (T / 64)];
@@ -1469,6 +1472,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
     if (!S->active) return;
     if (A.redo_only && !S->redo) return;
     const LenPlan& lp = A.lens[d.len_id];
+    // the DEF kernel is launched in place of the general one when every
+    // signal of the list is a four-step signal and stop mode 0 defers
+    const bool deferred = DEF || (SMODE == 0 && A.defer && !A.redo_only && lp.two_pass);
+    if (DEF && !lp.two_pass) return;
     const int64_t N = d.N;
     const int tid = threadIdx.x;
 
@@ -1517,8 +1524,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
     };
     // bins in groups of SG: the group's loads are issued together (memory
     // parallelism), the FP64 work of different groups is kept apart
-    // (register pressure)
-    constexpr int SG = 8;
+    // (register pressure).
+    constexpr int SG = DEF ? 4 : 8;
     static_assert(NR % SG == 0, "sweep groups");
 #pragma unroll
     for (int i0 = 0; i0 < NR; i0 += SG) {
@@ -1712,7 +1719,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs A)
     // ---- deferred FP64 check: four-step signals leave it to pass 1,
     //      which reads the spectrum and forms the powers anyway; k_verify
     //      accepts the estimate or sends the signal back here (redo_only)
-    if (SMODE == 0 && A.defer && !A.redo_only && lp.two_pass) {
+    if (deferred) {
         if (A.mt_shift) mt = max((int64_t)1, min(cap, mt + (int64_t)A.mt_shift));
         // the check in pass 1 counts the same bins as the FP64 evaluation here
         double mn_unused = INFINITY, qm = mz;

@@ -16,8 +16,13 @@ constexpr int kTileCapBig = 8192;
 // Threads of the FFT workgroups and of the scan workgroups.
 constexpr int kFftThreads = 512;
 constexpr int kScanThreads = 512;
-// Spectrum bins a scan thread keeps in registers (fast path: N <= 65536).
+// The one-workgroup scan (fast path: N/2 <= kScanBins bins, kept in
+// registers and LDS): bins per thread of the general kernel (512 threads) and
+// of the kernel for signals whose FP64 check is deferred to pass 1 (1024
+// threads: no FP64 search in it, so its registers allow 16 waves per CU).
+constexpr int kScanBins = 32768;
 constexpr int kScanBinsPerThread = 64;
+constexpr int kScanBinsDeferred = 32;
 constexpr int kMaxRadices = 24;
 // Most samples of a sampled window shape.
 constexpr int kMaxWindowPoints = 65537;
