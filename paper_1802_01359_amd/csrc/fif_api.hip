@@ -1216,8 +1216,11 @@ void launch_step_c(const fif_plan* p, Bound& b, int t, const T* x, T* imfs, void
             }
             V.redo_only = 1;
             if (g.ssmall.count) {
+                // the FP64 search from each rejected estimate (no FP32 state:
+                // the grid's other workgroups, returning at once, need no LDS)
                 V.list = small;
-                launch_k_scan<true, C>(0, g.ssmall.count, sizeof(float) * kScanBins, s, V, g);
+                k_scan<kScanBinsRedo, true, 0, C, false, true>
+                    <<<(unsigned)g.ssmall.count, kScanBins / kScanBinsRedo, 0, s>>>(V);
             }
             if (nb) {
                 // FP64 rounds of the multi-workgroup search for the signals

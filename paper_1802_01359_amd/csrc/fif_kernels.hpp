@@ -1454,10 +1454,13 @@ __device__ __forceinline__ int64_t geo_m(int q) { return q == 0 ? 1 : q == 1 ? 2
 // compile-time copy of ScanArgs::stop_mode, so the default kernel carries no
 // other mode's work).  DEF: the kernel for lists of four-step signals whose
 // FP64 check (stop mode 0) is deferred to pass 1 -- the FP32 search only.
-template <int BPT, bool PRE, int SMODE, typename C = double2, bool DEF = false>
+// RDO: the redo of the signals whose deferred estimate pass 1 rejected -- the
+// FP64 search only, from that estimate (no FP32 state: no dynamic LDS).
+template <int BPT, bool PRE, int SMODE, typename C = double2, bool DEF = false, bool RDO = false>
 __global__ __launch_bounds__(kScanBins / BPT) void k_scan(ScanArgs A)
 {
     static_assert(!DEF || SMODE == 0, "only stop mode 0 defers its check");
+    static_assert(!RDO || (PRE && SMODE == 0 && !DEF), "the redo follows a deferred stop-mode-0 check");
     constexpr int T = kScanBins / BPT;
     constexpr int NR = BPT;
     __shared__ RunState shr[T / 64];
@@ -1505,240 +1508,247 @@ __global__ __launch_bounds__(kScanBins / BPT) void k_scan(ScanArgs A)
     const float lnthr_abs = (float)log(delta * delta * (double)N * pscale);
     auto ok = [&](double sd) { return SMODE != 0 ? sd < delta : sd <= delta; };
     double mz = 0.0;          // largest |R_j|^2, j >= 1
-
-    // ---- first sweep: FP32 copies of the weighted power b, power*lambda^2
-    //      a, and tau = log2 mu, mu = (1 - lambda)^2 (DC kept aside since
-    //      lambda_0 = 1 contributes to m = 1 only) ----
-    float tau_r[NR], b_r[NR];
-    extern __shared__ float lds_a[];
     const SpecMap smap = make_specmap(lp);
     auto weight = [&](int j) -> double { return (2 * (int64_t)j == N) ? 1.0 : 2.0; };
-    // v: spectrum of bin jb; lambda in FP32 (this search only brackets m)
-    const float invNf = 1.f / (float)N, invLf = 1.f / (float)L;
-    auto sweep_bin = [&](double2 v, int64_t jb, float& tau, float& av, float& bv) {
-        const double P = weight(jb) * (v.x * v.x + v.y * v.y) * pscale;
-        const float lf = lambda_f32(jb, lw, invNf, invLf);
-        bv = (float)P;
-        av = bv * lf * lf;
-        tau = 2.8853900817779268f * log1pf(-lf);  // 2 log2(1 - lambda)
-    };
-    // bins in groups of SG: the group's loads are issued together (memory
-    // parallelism), the FP64 work of different groups is kept apart
-    // (register pressure).
-    constexpr int SG = DEF ? 4 : 8;
-    static_assert(NR % SG == 0, "sweep groups");
-#pragma unroll
-    for (int i0 = 0; i0 < NR; i0 += SG) {
-        double2 v[SG];
-        int64_t jb[SG];
-#pragma unroll
-        for (int g = 0; g < SG; ++g) {
-            const int j = 1 + tid + (i0 + g) * T;
-            v[g] = make_double2(0.0, 0.0);
-            jb[g] = 0;
-            if (j <= nh) {
-                v[g] = R[pos_small(smap, j)];
-                jb[g] = j;
-            }
-        }
-#pragma unroll
-        for (int g = 0; g < SG; ++g) {
-            const int i = i0 + g;
-            const int j = 1 + tid + i * T;
-            float av = 0.f;
-            tau_r[i] = 0.f;
-            b_r[i] = 0.f;
-            if (j <= nh) {
-                sweep_bin(v[g], jb[g], tau_r[i], av, b_r[i]);
-                // after the group's loads were issued, not between them
-                mz = fmax(mz, v[g].x * v[g].x + v[g].y * v[g].y);
-            }
-            lds_a[i * T + tid] = av;
-        }
-        __builtin_amdgcn_sched_barrier(0);
-    }
+
     const double P0 = (R[0].x * R[0].x + R[0].y * R[0].y) * pscale;
-    __syncthreads();
-
-    // per-bin FP32 accumulation of a*x and b*x, x = mu^e = 2^(e tau)
-    auto acc_bin = [&](float tau, float av, float bv, float e, float& sa, float& sb) {
-        const float xx = __builtin_amdgcn_exp2f(e * tau);
-        sa += av * xx;
-        sb += bv * xx;
-    };
-
-    // f at an arbitrary m (one FP32 pass); m = 1 needs no power (and must not
-    // form 0 * tau with tau = -inf for bins whose FP32 lambda rounds to 1)
-    auto f32 = [&](int64_t m) -> float {
-        float v[2] = {0.f, 0.f};
-        const float e = (float)(absm ? m : m - 1);
-        if (m == 1 && !absm) {
-#pragma unroll
-            for (int i = 0; i < NR; ++i) {
-                v[0] += lds_a[i * T + tid];
-                v[1] += b_r[i];
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < NR; ++i) acc_bin(tau_r[i], lds_a[i * T + tid], b_r[i], e, v[0], v[1]);
-        }
-        if (m == 1 && !absm && tid == 0) {
-            v[0] += (float)P0;
-            v[1] += (float)P0;
-        }
-        block_sum<float, T, 2>(v, shf);
-        n32 += 1;
-        if (absm) return v[0] > 0.f ? (logf(v[0]) - lnthr_abs) : -INFINITY;
-        return v[1] > 0.f ? (logf(v[0] / v[1]) - lnd2) : -INFINITY;
-    };
-
-    // ---- bracket by probing m = 1, 2, 4, 16, 64, ... (one FP32 pass each,
-    //      stopping at the first that satisfies the test), then safeguarded
-    //      regula falsi: smallest m <= cap with f(m) <= 0 (f is
-    //      non-increasing in m)
-    int64_t mt;
+    int64_t mt = 0;
     uint32_t flags = 0;
-    if (SMODE == 2) {
-        double mn_unused = INFINITY, mzb = fmax(mz, P0 / pscale);
-        block_minmax<T>(mn_unused, mzb, shd);
-        const int64_t n0 = apriori_n0(mzb, L, N, delta);
-        mt = n0;
-        if (mt > cap) {
-            mt = cap;
-            flags |= FIF_IMF_CAP;
-        }
+    if constexpr (RDO) {
+        // the redo after a rejected deferred estimate: the FP64 search
+        // below starts from that estimate (the FP32 search would only
+        // find it again)
+        mt = S->m;
     } else {
-        int64_t lo = 0, hi = -1;
-        float flo = INFINITY, fhi = 0.f;
-        const int64_t mp = A.prop ? A.prop[s] : 0;
-        int64_t top = cap;        // largest count the FP32 search considers
-        if (mp > 0) {
-            // bracket from the proposal: probe it, then walk away from it
-            // in steps growing fourfold from mp/16 until f changes sign
-            int64_t c = min(mp, cap);
-            int64_t step = max((int64_t)1, c >> 4);
-            float fc = f32(c);
-            if (fc <= 0.f) {
-                hi = c;
-                fhi = fc;
-                while (hi > 1) {
-                    c = max((int64_t)1, hi - step);
-                    fc = f32(c);
-                    if (fc > 0.f) {
-                        lo = c;
-                        flo = fc;
-                        break;
-                    }
-                    hi = c;
-                    fhi = fc;
-                    step *= 4;
+        // ---- first sweep: FP32 copies of the weighted power b, power*lambda^2
+        //      a, and tau = log2 mu, mu = (1 - lambda)^2 (DC kept aside since
+        //      lambda_0 = 1 contributes to m = 1 only) ----
+        float tau_r[NR], b_r[NR];
+        extern __shared__ float lds_a[];
+        // v: spectrum of bin jb; lambda in FP32 (this search only brackets m)
+        const float invNf = 1.f / (float)N, invLf = 1.f / (float)L;
+        auto sweep_bin = [&](double2 v, int64_t jb, float& tau, float& av, float& bv) {
+            const double P = weight(jb) * (v.x * v.x + v.y * v.y) * pscale;
+            const float lf = lambda_f32(jb, lw, invNf, invLf);
+            bv = (float)P;
+            av = bv * lf * lf;
+            tau = 2.8853900817779268f * log1pf(-lf);  // 2 log2(1 - lambda)
+        };
+        // bins in groups of SG: the group's loads are issued together (memory
+        // parallelism), the FP64 work of different groups is kept apart
+        // (register pressure).
+        constexpr int SG = DEF ? 4 : 8;
+        static_assert(NR % SG == 0, "sweep groups");
+#pragma unroll
+        for (int i0 = 0; i0 < NR; i0 += SG) {
+            double2 v[SG];
+            int64_t jb[SG];
+#pragma unroll
+            for (int g = 0; g < SG; ++g) {
+                const int j = 1 + tid + (i0 + g) * T;
+                v[g] = make_double2(0.0, 0.0);
+                jb[g] = 0;
+                if (j <= nh) {
+                    v[g] = R[pos_small(smap, j)];
+                    jb[g] = j;
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < SG; ++g) {
+                const int i = i0 + g;
+                const int j = 1 + tid + i * T;
+                float av = 0.f;
+                tau_r[i] = 0.f;
+                b_r[i] = 0.f;
+                if (j <= nh) {
+                    sweep_bin(v[g], jb[g], tau_r[i], av, b_r[i]);
+                    // after the group's loads were issued, not between them
+                    mz = fmax(mz, v[g].x * v[g].x + v[g].y * v[g].y);
+                }
+                lds_a[i * T + tid] = av;
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        __syncthreads();
+
+        // per-bin FP32 accumulation of a*x and b*x, x = mu^e = 2^(e tau)
+        auto acc_bin = [&](float tau, float av, float bv, float e, float& sa, float& sb) {
+            const float xx = __builtin_amdgcn_exp2f(e * tau);
+            sa += av * xx;
+            sb += bv * xx;
+        };
+
+        // f at an arbitrary m (one FP32 pass); m = 1 needs no power (and must not
+        // form 0 * tau with tau = -inf for bins whose FP32 lambda rounds to 1)
+        auto f32 = [&](int64_t m) -> float {
+            float v[2] = {0.f, 0.f};
+            const float e = (float)(absm ? m : m - 1);
+            if (m == 1 && !absm) {
+#pragma unroll
+                for (int i = 0; i < NR; ++i) {
+                    v[0] += lds_a[i * T + tid];
+                    v[1] += b_r[i];
                 }
             } else {
-                lo = c;
-                flo = fc;
-                while (lo < cap) {
-                    c = min(cap, lo + step);
-                    fc = f32(c);
+#pragma unroll
+                for (int i = 0; i < NR; ++i) acc_bin(tau_r[i], lds_a[i * T + tid], b_r[i], e, v[0], v[1]);
+            }
+            if (m == 1 && !absm && tid == 0) {
+                v[0] += (float)P0;
+                v[1] += (float)P0;
+            }
+            block_sum<float, T, 2>(v, shf);
+            n32 += 1;
+            if (absm) return v[0] > 0.f ? (logf(v[0]) - lnthr_abs) : -INFINITY;
+            return v[1] > 0.f ? (logf(v[0] / v[1]) - lnd2) : -INFINITY;
+        };
+
+        // ---- bracket by probing m = 1, 2, 4, 16, 64, ... (one FP32 pass each,
+        //      stopping at the first that satisfies the test), then safeguarded
+        //      regula falsi: smallest m <= cap with f(m) <= 0 (f is
+        //      non-increasing in m)
+        if (SMODE == 2) {
+            double mn_unused = INFINITY, mzb = fmax(mz, P0 / pscale);
+            block_minmax<T>(mn_unused, mzb, shd);
+            const int64_t n0 = apriori_n0(mzb, L, N, delta);
+            mt = n0;
+            if (mt > cap) {
+                mt = cap;
+                flags |= FIF_IMF_CAP;
+            }
+        } else {
+            int64_t lo = 0, hi = -1;
+            float flo = INFINITY, fhi = 0.f;
+            const int64_t mp = A.prop ? A.prop[s] : 0;
+            int64_t top = cap;        // largest count the FP32 search considers
+            if (mp > 0) {
+                // bracket from the proposal: probe it, then walk away from it
+                // in steps growing fourfold from mp/16 until f changes sign
+                int64_t c = min(mp, cap);
+                int64_t step = max((int64_t)1, c >> 4);
+                float fc = f32(c);
+                if (fc <= 0.f) {
+                    hi = c;
+                    fhi = fc;
+                    while (hi > 1) {
+                        c = max((int64_t)1, hi - step);
+                        fc = f32(c);
+                        if (fc > 0.f) {
+                            lo = c;
+                            flo = fc;
+                            break;
+                        }
+                        hi = c;
+                        fhi = fc;
+                        step *= 4;
+                    }
+                } else {
+                    lo = c;
+                    flo = fc;
+                    while (lo < cap) {
+                        c = min(cap, lo + step);
+                        fc = f32(c);
+                        if (fc <= 0.f) {
+                            hi = c;
+                            fhi = fc;
+                            break;
+                        }
+                        lo = c;
+                        flo = fc;
+                        step *= 4;
+                    }
+                }
+            } else {
+                // stop mode 1: Theorem 5's N0 satisfies the absolute test, so
+                // the search needs no probe above it (Section 4 scans up to N0)
+                if (SMODE == 1) {
+                    double mn_unused = INFINITY, mzb = fmax(mz, P0 / pscale);
+                    block_minmax<T>(mn_unused, mzb, shd);
+                    top = min(cap, apriori_n0(mzb, L, N, delta));
+                }
+                for (int q = 0; q < kGeo; ++q) {
+                    const int64_t mq = geo_m(q);
+                    if (mq >= top) break;
+                    const float fq = f32(mq);
+                    if (fq <= 0.f) {
+                        hi = mq;
+                        fhi = fq;
+                        break;
+                    }
+                    lo = mq;
+                    flo = fq;
+                }
+                if (hi < 0) {
+                    // no probe below the top satisfies the test
+                    const float fc = f32(top);
+                    if (fc <= 0.f) {
+                        hi = top;
+                        fhi = fc;
+                    } else {
+                        lo = top;
+                    }
+                }
+            }
+            if (hi < 0) {
+                mt = top;
+            } else {
+                int side = 0;  // Illinois: endpoint kept twice in a row gets its f halved
+                int64_t last_width = hi - lo;
+                bool bisect = false;
+                while (hi - lo > 1) {
+                    int64_t c;
+                    if (bisect || lo == 0 || !isfinite(flo)) {
+                        c = lo + (hi - lo) / 2;
+                    } else {
+                        const double fr = (double)flo / ((double)flo - (double)fhi);
+                        c = lo + (int64_t)llrint(fr * (double)(hi - lo));
+                    }
+                    c = max(lo + 1, min(hi - 1, c));
+                    const float fc = f32(c);
                     if (fc <= 0.f) {
                         hi = c;
                         fhi = fc;
-                        break;
+                        if (side == 1) flo *= 0.5f;
+                        side = 1;
+                    } else {
+                        lo = c;
+                        flo = fc;
+                        if (side == -1) fhi *= 0.5f;
+                        side = -1;
                     }
-                    lo = c;
-                    flo = fc;
-                    step *= 4;
+                    // force a bisection step when the bracket shrank less than half
+                    const int64_t wdt = hi - lo;
+                    bisect = (2 * wdt > last_width);
+                    last_width = wdt;
                 }
-            }
-        } else {
-            // stop mode 1: Theorem 5's N0 satisfies the absolute test, so
-            // the search needs no probe above it (Section 4 scans up to N0)
-            if (SMODE == 1) {
-                double mn_unused = INFINITY, mzb = fmax(mz, P0 / pscale);
-                block_minmax<T>(mn_unused, mzb, shd);
-                top = min(cap, apriori_n0(mzb, L, N, delta));
-            }
-            for (int q = 0; q < kGeo; ++q) {
-                const int64_t mq = geo_m(q);
-                if (mq >= top) break;
-                const float fq = f32(mq);
-                if (fq <= 0.f) {
-                    hi = mq;
-                    fhi = fq;
-                    break;
-                }
-                lo = mq;
-                flo = fq;
-            }
-            if (hi < 0) {
-                // no probe below the top satisfies the test
-                const float fc = f32(top);
-                if (fc <= 0.f) {
-                    hi = top;
-                    fhi = fc;
-                } else {
-                    lo = top;
-                }
+                mt = hi;
             }
         }
-        if (hi < 0) {
-            mt = top;
-        } else {
-            int side = 0;  // Illinois: endpoint kept twice in a row gets its f halved
-            int64_t last_width = hi - lo;
-            bool bisect = false;
-            while (hi - lo > 1) {
-                int64_t c;
-                if (bisect || lo == 0 || !isfinite(flo)) {
-                    c = lo + (hi - lo) / 2;
-                } else {
-                    const double fr = (double)flo / ((double)flo - (double)fhi);
-                    c = lo + (int64_t)llrint(fr * (double)(hi - lo));
-                }
-                c = max(lo + 1, min(hi - 1, c));
-                const float fc = f32(c);
-                if (fc <= 0.f) {
-                    hi = c;
-                    fhi = fc;
-                    if (side == 1) flo *= 0.5f;
-                    side = 1;
-                } else {
-                    lo = c;
-                    flo = fc;
-                    if (side == -1) fhi *= 0.5f;
-                    side = -1;
-                }
-                // force a bisection step when the bracket shrank less than half
-                const int64_t wdt = hi - lo;
-                bisect = (2 * wdt > last_width);
-                last_width = wdt;
-            }
-            mt = hi;
-        }
-    }
 
-    // ---- deferred FP64 check: four-step signals leave it to pass 1,
-    //      which reads the spectrum and forms the powers anyway; k_verify
-    //      accepts the estimate or sends the signal back here (redo_only)
-    if (deferred) {
-        if (A.mt_shift) mt = max((int64_t)1, min(cap, mt + (int64_t)A.mt_shift));
-        // the check in pass 1 counts the same bins as the FP64 evaluation here
-        double mn_unused = INFINITY, qm = mz;
-        block_minmax<T>(mn_unused, qm, shd);
-        if (tid == 0) {
-            S->L = L;
-            S->m = mt;
-            S->chk = 1;
-            S->qthr = kSdNoise * qm;
-            if (A.info) {
-                fif_imf_info* I = A.info + (int64_t)s * A.max_imfs + A.t;
-                I->k = S->k;
-                I->L = L;
-                I->m = mt;
-                I->flags = 0;
-                I->evals = (n32 & 0xffffu) | (1u << 16);
+        // ---- deferred FP64 check: four-step signals leave it to pass 1,
+        //      which reads the spectrum and forms the powers anyway; k_verify
+        //      accepts the estimate or sends the signal back here (redo_only)
+        if (deferred) {
+            if (A.mt_shift) mt = max((int64_t)1, min(cap, mt + (int64_t)A.mt_shift));
+            // the check in pass 1 counts the same bins as the FP64 evaluation here
+            double mn_unused = INFINITY, qm = mz;
+            block_minmax<T>(mn_unused, qm, shd);
+            if (tid == 0) {
+                S->L = L;
+                S->m = mt;
+                S->chk = 1;
+                S->qthr = kSdNoise * qm;
+                if (A.info) {
+                    fif_imf_info* I = A.info + (int64_t)s * A.max_imfs + A.t;
+                    I->k = S->k;
+                    I->L = L;
+                    I->m = mt;
+                    I->flags = 0;
+                    I->evals = (n32 & 0xffffu) | (1u << 16);
+                }
             }
+            return;
         }
-        return;
     }
 
     // ---- FP64 SD at m and m-1 (Parseval, FP64 lambda, powers and sums).
@@ -1751,7 +1761,7 @@ __global__ __launch_bounds__(kScanBins / BPT) void k_scan(ScanArgs A)
     //      exponent, as in a streaming log-sum-exp), so that the sums never
     //      underflow and SD tends to the smallest counted lambda, as in exact
     //      arithmetic.  The FP32 search above only brackets m; this decides.
-    double qthr = -1.0;
+    double qthr = RDO ? S->qthr : -1.0;   // the noise floor the deferred check used
     auto sd64 = [&](int64_t m, double& sd_m, double& sd_mm1) {
         if (SMODE == 0 && qthr < 0.0) {
             double mn_unused = INFINITY, qm = mz;

@@ -23,6 +23,10 @@ constexpr int kScanThreads = 512;
 constexpr int kScanBins = 32768;
 constexpr int kScanBinsPerThread = 64;
 constexpr int kScanBinsDeferred = 32;
+// The redo of a rejected deferred estimate (FP64 search only, no bins kept):
+// 256 threads, so that the grid's workgroups, nearly all returning at once,
+// fit three to a CU.
+constexpr int kScanBinsRedo = 128;
 constexpr int kMaxRadices = 24;
 // Most samples of a sampled window shape.
 constexpr int kMaxWindowPoints = 65537;
