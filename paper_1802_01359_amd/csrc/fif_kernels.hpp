@@ -338,6 +338,17 @@ __device__ __forceinline__ Lam make_lam(const LenPlan& lp, const double* dtab, i
 __device__ __forceinline__ double sin_u(int64_t u, int64_t N) { return sinpi((double)u / (double)N); }
 __device__ __forceinline__ double isin_u(int64_t u, int64_t N) { return 1.0 / sinpi((double)u / (double)N); }
 
+// t = L j mod N folded into [0, N/2] (N <= 2^26, every plan length): for a
+// power of two the low 32 bits of the product decide it, otherwise the FP64
+// quotient does (mulmod53).
+__device__ __forceinline__ int lam_arg(int64_t j, const Lam& w)
+{
+    const int t = w.mask ? (int)(((uint32_t)w.Lmod * (uint32_t)j) & (uint32_t)w.mask)
+                         : (int)mulmod53(w.Lmod, j, w.N, w.invN);
+    const int n = (int)w.N;
+    return min(t, n - t);
+}
+
 // lambda_j = [sin(pi L j / N) / (L sin(pi j / N))]^4, the DFT of the
 // circulant column of the triangle-squared window, with L*j reduced mod N
 // exactly; the sines come from the tables or are evaluated in place.
@@ -345,8 +356,7 @@ __device__ __forceinline__ double lambda_at(int64_t j, const Lam& w)
 {
     if (j == 0) return 1.0;
     if (w.tab) return w.tab[j];
-    int64_t t = w.mask ? ((w.Lmod * j) & w.mask) : mulmod53(w.Lmod, j, w.N, w.invN);
-    if (t > w.N - t) t = w.N - t;
+    const int t = lam_arg(j, w);
     const double st = w.inl ? sin_u(t, w.N) : w.sinT[t];
     const double is = w.inl == 2 ? isin_u(j, w.N) : w.isinT[j];
     const double q = st * is * w.invL;
@@ -364,8 +374,7 @@ __device__ __forceinline__ float lambda_f32(int64_t j, const Lam& w, float invNf
 {
     if (j == 0) return 1.f;
     if (w.tab) return (float)w.tab[j];
-    int64_t t = w.mask ? ((w.Lmod * j) & w.mask) : mulmod53(w.Lmod, j, w.N, w.invN);
-    if (t > w.N - t) t = w.N - t;
+    const int t = lam_arg(j, w);
     const float is = ISIN ? 1.f / sinpif((float)j * invNf) : (float)w.isinT[j];
     const float q = sinpif((float)t * invNf) * is * invLf;
     const float q2 = q * q;
@@ -900,7 +909,7 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
                     r = N2 >> 1;
                 }
                 const int c = pass1_col(pr, w.tile, s);
-                const int64_t k = c + (int64_t)N1 * r;
+                const int k = c + N1 * r;      // N <= 2^26: bin indices fit in 32 bits
                 const int64_t pk = (f < owners) ? pbase + f : (N >> 1);
                 const double2 v = to_d(vv[q]);
                 double g = 0.0;
@@ -961,9 +970,9 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
             for (int f = threadIdx.x; f < total; f += kFftThreads) {
                 int s;
                 const int r = fdivmod(f, ftc, s);
-                const int64_t k = pass1_col(pr, w.tile, s) + (int64_t)N1 * r;
+                const int k = pass1_col(pr, w.tile, s) + N1 * r;   // N <= 2^26
                 const bool mirror = k > nh;
-                const int64_t j = mirror ? N - k : k;
+                const int j = mirror ? (int)N - k : k;
                 const double2 v = to_d(Rin[j]);
                 double g = 0.0;
                 if (MODE == MODE_STEP) {
