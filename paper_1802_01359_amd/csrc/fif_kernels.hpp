@@ -262,6 +262,17 @@ __device__ __forceinline__ void block_sum(T* v, T* sh)
     __syncthreads();
 }
 
+// Work item of workgroup b in a grid of G: workgroups are dispatched to the
+// eight XCDs in turn (b mod 8), so consecutive items are given to workgroups
+// b, b + 8, ... of one XCD: the items of one signal then share that XCD's L2,
+// where their partial-line writes (64-byte IMF runs, 12-byte run summaries)
+// merge before they reach HBM.  A bijection of [0, G).
+__device__ __forceinline__ int xcd_item(int b, int G)
+{
+    const int per = G >> 3, rem = G & 7, x = b & 7;
+    return x * per + min(x, rem) + (b >> 3);
+}
+
 // min and max over the block, result in every thread
 template <int NT>
 __device__ __forceinline__ void block_minmax(double& mn, double& mx, double* sh)
@@ -1198,7 +1209,7 @@ __global__ __launch_bounds__(kFftThreads) void k_pass2(StepArgs A, const InT* __
     extern __shared__ double2 lds_raw[];
     C* lds = reinterpret_cast<C*>(lds_raw);
     __shared__ double shd[2 * (kFftThreads / 64)];
-    const P2Item t = p2_item(A, blockIdx.x);
+    const P2Item t = p2_item(A, xcd_item(blockIdx.x, gridDim.x));
     const SigDesc& d = t.d;
     const LenPlan& lp = *t.lp;
     const int64_t N = d.N;
