@@ -26,7 +26,7 @@ def _same(a, b):
             and torch.equal(a.sig_status, b.sig_status))
 
 
-@pytest.mark.skip(reason="kept off the GPU for the rest of this round: its first run faulted the GPU "
+@pytest.mark.skip(reason="kept off the GPU: its first run faulted the GPU "
                          "(a library built from mixed sources: device StepArgs 136 bytes, host 152) and the "
                          "run that tested the consistent rebuild aborted at plan creation (a const device "
                          "array the runtime could not resolve); both causes shown on the CPU and fixed")
