@@ -334,8 +334,16 @@ def test_long_signal_full_size():
     record("long-1x16777216 fp32", 0.0, imfs=0, signals=1)
 
 
+# with a one-pass length (4096) beside the four-step ones, and without: a
+# group whose one-workgroup scan list holds only four-step signals runs the
+# 1024-thread scan kernel without the FP64 search
+REDO_LENGTHS = {"mixed": [65536, 65536, 16384, 4096, 12000, 10125, 131072, 98415],
+                "four_step": [65536, 16384, 12000, 10125, 131072, 98415]}
+
+
+@pytest.mark.parametrize("kind", sorted(REDO_LENGTHS))
 @pytest.mark.parametrize("shift", [1, -1])
-def test_deferred_check_redo_path(shift, monkeypatch):
+def test_deferred_check_redo_path(shift, kind, monkeypatch):
     """The FP64 check of m for four-step signals runs inside pass 1; when it
     fails the step is redone (exact search, pass 1 again; for signals of the
     multi-workgroup search its FP64 rounds). A host-side hook shifts every
@@ -344,10 +352,10 @@ def test_deferred_check_redo_path(shift, monkeypatch):
     (but m = 1 shifted down, which stays 1 and passes).  Lengths: paired and
     unpaired four-step plans (10125 = 3^4 5^3), and the multi-workgroup search
     with paired (131072) and unpaired (98415 = 3^9 5) plans."""
-    lengths = [65536, 65536, 16384, 4096, 12000, 10125, 131072, 98415]
+    lengths = REDO_LENGTHS[kind]
     sigs = [siggen.chirps(i).astype(np.float32) if N == 65536 else _signal(N, 900 + i).astype(np.float32)
             for i, N in enumerate(lengths)]
-    print("case deferred check shift=%d" % shift, flush=True)
+    print("case deferred check shift=%d lengths %s" % (shift, lengths), flush=True)
     plan0, packed, ref = _run_batch(lengths, sigs, 1e-3, 6, torch.float32)
     monkeypatch.setenv("FIF_DEBUG_MT_SHIFT", str(shift))
     plan1, _, out = _run_batch(lengths, sigs, 1e-3, 6, torch.float32)
