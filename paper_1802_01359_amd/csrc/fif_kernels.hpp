@@ -861,7 +861,10 @@ __global__ __launch_bounds__(kFftThreads) void k_pass1(StepArgs A, const InT* __
 {
     extern __shared__ double2 lds_raw[];
     C* lds = reinterpret_cast<C*>(lds_raw);
-    const Work w = A.work[blockIdx.x];
+    // the forward transforms gather the input in runs of TC/2 samples, so
+    // neighbouring tiles read parts of the same cache lines: their workgroups
+    // share an XCD (and its L2) there; the step passes keep the plain order
+    const Work w = A.work[fwd_mode(MODE) ? xcd_item(blockIdx.x, gridDim.x) : blockIdx.x];
     const SigDesc d = A.sigs[w.sig];
     const LenPlan& lp = A.lens[d.len_id];
     const PlanRegs pr = plan_regs(lp);
